@@ -1,0 +1,170 @@
+/*
+ * gamer_hydro.h -- C ABI of the MI355X (gfx950) MUSCL-Hancock + Roe hydro solver
+ * for batches of ghost-padded 16^3 patch groups.
+ *
+ * The method is the GPU hydrodynamic solver of "GAMER with out-of-core
+ * computation" (Schive, Tsai & Chiueh), Sec. 2: the MUSCL-Hancock scheme in
+ * four steps (spatial data reconstruction, half-step prediction, Riemann
+ * solver, full-step update), applied unsplit in 3D, with Roe's Riemann
+ * solver and a five-point stencil per direction, i.e. two ghost cells per
+ * side of every patch group.  The paper's Sec. 2 also states the division
+ * of labour kept here: the host prepares ghost-padded groups, the GPU
+ * advances them.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers owned by the caller, unless an
+ *    argument says otherwise.  The library never frees or retains them.
+ *  - Layouts are C-contiguous with x fastest:
+ *      padded group    [n][5][20][20][20]  conserved (rho, m_x, m_y, m_z, E),
+ *                                          cell (i,j,k) at i,j,k = -2..17
+ *      interior group  [n][5][16][16][16]  cells 0..15
+ *      flux planes     [n][3 dir][3 plane][5][16][16]: the flux density F_d
+ *                      (not multiplied by dt or area) on the faces with index
+ *                      0, 8 and 16 along d (face f lies between cells f-1 and
+ *                      f: the two outer faces and the mid-plane between the
+ *                      2x2x2 sibling 8^3 patches); transverse order (k,j)
+ *                      for x, (k,i) for y, (j,i) for z.
+ *      group stats     [n][8] doubles: sum rho, sum m_x, sum m_y, sum m_z,
+ *                      sum E over the 16^3 output cells (not multiplied by
+ *                      dh^3), max over output cells of |u|+|v|+|w|+3 c_s,
+ *                      number of cells whose half-step prediction fell back
+ *                      to first order, number of faces whose Roe flux fell
+ *                      back to HLLE.
+ *  - Ideal gas, p = (gamma - 1)(E - rho |u|^2 / 2), c_s = sqrt(gamma p / rho).
+ *  - Every call is asynchronous and ordered on the calling host thread's
+ *    current stream (gamer_set_stream; default: the null stream).  Errors a
+ *    kernel meets later surface at the next synchronising call.
+ *  - Return value: GAMER_OK (0) or a negative code; gamer_last_error() then
+ *    holds a message (per host thread).  n_groups == 0 is a successful no-op.
+ *  - Inputs and outputs must not overlap.
+ *  - Non-physical intermediate states are not errors: the solver falls back
+ *    (first-order prediction for the cell, HLLE for the face) and counts them
+ *    in the group stats.
+ *  - FP32 entry points (suffix _f32) store and compute in float, but form
+ *    the full-step update U - dt/dh * sum(dF) and all sums in double,
+ *    rounding once on store.
+ */
+#ifndef GAMER_HYDRO_H
+#define GAMER_HYDRO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GAMER_OK 0
+#define GAMER_EINVAL (-1) /* invalid argument: nothing was launched */
+#define GAMER_EHIP (-2)   /* a HIP runtime call failed; see gamer_last_error() */
+#define GAMER_ENOMEM (-3) /* the library could not allocate its scratch space */
+
+#define GAMER_MAX_LEVELS 32 /* largest n_levels of the batched entry points */
+
+/* Tunables of the reading of the method.  NULL selects the defaults. */
+typedef struct gamer_opts {
+    /* Generalised-minmod parameter of the slope limiter, 1 <= theta <= 2
+     * (1: minmod, 2: monotonised central).  Default 1.5. */
+    double theta;
+} gamer_opts;
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int gamer_version(void);
+
+/* Make `hip_stream` (a hipStream_t, may be NULL for the null stream) the
+ * stream of every later call from this host thread. */
+int gamer_set_stream(void *hip_stream);
+void *gamer_get_stream(void);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char *gamer_last_error(void);
+
+/* ---- one MUSCL-Hancock + Roe step (paper Sec. 2, all four steps) --------
+ * Advances every padded group in `groups_in` by dt with cell size dh and
+ * writes the 16^3 interior to `groups_out`.  Per group:
+ *   1. reconstruction: primitive variables, generalised-minmod limited
+ *      slopes along x, y, z on the interior plus one ghost layer per face;
+ *   2. half-step prediction: the conservative Hancock step with the flux
+ *      differences of all three directions added to all six face states;
+ *   3. Roe fluxes (Harten-Hyman entropy fix; HLLE when an intermediate
+ *      state is unphysical) at the 3 x 17 x 16 x 16 faces;
+ *   4. full-step update U^{n+1} = U^n - dt/dh sum_d (F_{d,+} - F_{d,-}).
+ * `fluxes_out` may be NULL.  Errors: GAMER_EINVAL for n_groups < 0, a NULL
+ * array with n_groups > 0, dt or dh not finite and positive, gamma <= 1. */
+int gamer_hydro_solve(const double *groups_in, int64_t n_groups, double dt, double dh,
+                      double gamma, double *fluxes_out, double *groups_out);
+int gamer_hydro_solve_f32(const float *groups_in, int64_t n_groups, double dt, double dh,
+                          double gamma, float *fluxes_out, float *groups_out);
+
+/* ---- batched step over groups of uneven refinement level ---------------
+ * Same step as gamer_hydro_solve in ONE launch, with each group's dt and dh
+ * read ON THE DEVICE: group g uses dt_dev[level[g]] and dh_dev[level[g]]
+ * (level == NULL: every group uses level 0), so a captured HIP graph can be
+ * replayed while dt changes.  level: device int8 [n_groups], values in
+ * 0..n_levels-1 (not checked on the device).  dt_dev, dh_dev: device double
+ * [n_levels], 1 <= n_levels <= GAMER_MAX_LEVELS.  group_stats: device double
+ * [n_groups][8] (see conventions) or NULL.  opts may be NULL. */
+int gamer_hydro_solve_batched(const double *groups_in, int64_t n_groups, const int8_t *level,
+                              const double *dt_dev, const double *dh_dev, int n_levels,
+                              double gamma, double *fluxes_out, double *groups_out,
+                              double *group_stats, const gamer_opts *opts);
+int gamer_hydro_solve_batched_f32(const float *groups_in, int64_t n_groups, const int8_t *level,
+                                  const double *dt_dev, const double *dh_dev, int n_levels,
+                                  double gamma, float *fluxes_out, float *groups_out,
+                                  double *group_stats, const gamer_opts *opts);
+
+/* ---- reduction of group stats to time steps and totals -----------------
+ * From group_stats [n_groups][8] (as written by the batched step or by
+ * gamer_group_stats), computes on the device, in a fixed order (results are
+ * bitwise reproducible):
+ *   dt_dev_out[L] = cfl * dh_dev[L] / max over groups of level L of stat 5
+ *                   (+inf when level L has no group or a zero maximum);
+ *   totals_dev_out[0..4] = sum over groups of dh_dev[level]^3 * stats 0..4,
+ *   totals_dev_out[5..6] = sum over groups of stats 6..7.
+ * Either output may be NULL.  level, dh_dev, n_levels as in the batched step.
+ * Errors: GAMER_EINVAL for cfl not finite and positive, bad sizes. */
+int gamer_step_reduce(const double *group_stats, int64_t n_groups, const int8_t *level,
+                      const double *dh_dev, int n_levels, double cfl, double *dt_dev_out,
+                      double *totals_dev_out);
+
+/* ---- per-group stats of interior groups --------------------------------
+ * group_stats [n][8] for interior groups [n][5][16][16][16] (stats 6, 7 set to 0). */
+int gamer_group_stats(const double *groups, int64_t n_groups, double gamma, double *group_stats);
+int gamer_group_stats_f32(const float *groups, int64_t n_groups, double gamma,
+                          double *group_stats);
+
+/* ---- CFL time step ------------------------------------------------------
+ * dt = cfl * dh / max over all interior cells of (|u| + |v| + |w| + 3 c_s), the
+ * 3D unsplit stability bound (the paper does not state its CFL form).
+ * groups: interior [n][5][16][16][16].  dt_out is a device pointer when
+ * dt_out_is_device != 0 (asynchronous), else a host pointer (the call then
+ * synchronises the stream).  Uses library scratch of 64 B per group. */
+int gamer_cfl_dt(const double *groups, int64_t n_groups, double dh, double gamma, double cfl,
+                 double *dt_out, int dt_out_is_device);
+int gamer_cfl_dt_f32(const float *groups, int64_t n_groups, double dh, double gamma, double cfl,
+                     double *dt_out, int dt_out_is_device);
+
+/* ---- conserved totals ---------------------------------------------------
+ * sums5_out = dh^3 (sum rho, sum m_x, sum m_y, sum m_z, sum E) over interior
+ * groups [n][5][16][16][16], accumulated in double in a fixed order.
+ * Device pointer when is_device != 0, else host (synchronising). */
+int gamer_conserved_sums(const double *groups, int64_t n_groups, double dh, double *sums5_out,
+                         int is_device);
+int gamer_conserved_sums_f32(const float *groups, int64_t n_groups, double dh,
+                             double *sums5_out, int is_device);
+
+/* ---- same-level periodic ghost fill (harness utility) -------------------
+ * state: interior groups of a uniform periodic grid of gx x gy x gz groups,
+ * [gx*gy*gz][5][16][16][16] with group index g = x + gx (y + gy z).
+ * padded: [gx*gy*gz][5][20][20][20]; each padded cell takes the value of
+ * the cell at its periodically wrapped global position.  The paper prepares
+ * ghost zones on the host from the AMR hierarchy; this covers the uniform
+ * periodic case on the device.  Errors: GAMER_EINVAL for gx, gy, gz < 1. */
+int gamer_pack_periodic(const double *state, int gx, int gy, int gz, double *padded);
+int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *padded);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAMER_HYDRO_H */

@@ -1,0 +1,215 @@
+"""FP64 CPU oracle for the MUSCL-Hancock + Roe group step -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``libgamer_oracle.so`` (plain C,
+see ``gamer_oracle.c``) with numpy arrays on the host.  It shares no code with
+the HIP library.
+
+Array conventions (all float64, C-contiguous, x fastest):
+  padded groups   (n, 5, 20, 20, 20)  conserved (rho, m_x, m_y, m_z, E)
+  interior groups (n, 5, 16, 16, 16)
+  flux planes     (n, 3, 3, 5, 16, 16)
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+_D = ctypes.c_double
+_PD = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.c_int64
+_PLL = ctypes.POINTER(ctypes.c_longlong)
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_build.LIB) or (
+                os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
+            _build.build()
+        lib = ctypes.CDLL(_build.LIB)
+        sig = {
+            "gamer_oracle_set_threads": (None, [ctypes.c_int]),
+            "gamer_oracle_get_threads": (ctypes.c_int, []),
+            "gamer_oracle_prim_from_cons": (None, [_PD, _D, _PD]),
+            "gamer_oracle_cons_from_prim": (None, [_PD, _D, _PD]),
+            "gamer_oracle_phys_flux": (None, [_PD, ctypes.c_int, _D, _PD]),
+            "gamer_oracle_limiter": (_D, [_D, _D, _D]),
+            "gamer_oracle_group_prim": (None, [_PD, _D, _PD]),
+            "gamer_oracle_group_slopes": (None, [_PD, _D, _PD]),
+            "gamer_oracle_group_predict": (ctypes.c_longlong, [_PD, _PD, _PD, _D, _D, _D, _PD]),
+            "gamer_oracle_group_fluxes": (ctypes.c_longlong, [_PD, _D, _PD]),
+            "gamer_oracle_group_update": (None, [_PD, _PD, _D, _D, _PD, _PD]),
+            "gamer_oracle_roe_flux": (ctypes.c_int, [_PD, _PD, ctypes.c_int, _D, _PD]),
+            "gamer_oracle_roe_decompose": (None, [_PD, _PD, _D, _PD, _PD, _PD, _PD]),
+            "gamer_oracle_hydro_solve": (ctypes.c_int, [_PD, _I64, _D, _D, _D, _D, _PD, _PD, _PLL]),
+            "gamer_oracle_max_speed": (_D, [_PD, _I64, _D]),
+            "gamer_oracle_cfl_dt": (_D, [_PD, _I64, _D, _D, _D]),
+            "gamer_oracle_conserved_sums": (None, [_PD, _I64, _D, _PD]),
+            "gamer_oracle_pack_periodic": (None, [_PD, ctypes.c_int, ctypes.c_int, ctypes.c_int, _PD]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_PD)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+THETA = 1.5  # generalised-minmod parameter of the default reading
+
+
+def set_threads(n: int) -> None:
+    _lib().gamer_oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return _lib().gamer_oracle_get_threads()
+
+
+# --- single-state helpers ---------------------------------------------------
+
+def prim_from_cons(U, gamma):
+    U = _f64(U)
+    W = np.empty(5)
+    _lib().gamer_oracle_prim_from_cons(_p(U), gamma, _p(W))
+    return W
+
+
+def cons_from_prim(W, gamma):
+    W = _f64(W)
+    U = np.empty(5)
+    _lib().gamer_oracle_cons_from_prim(_p(W), gamma, _p(U))
+    return U
+
+
+def phys_flux(U, d, gamma):
+    U = _f64(U)
+    F = np.empty(5)
+    _lib().gamer_oracle_phys_flux(_p(U), int(d), gamma, _p(F))
+    return F
+
+
+def limiter(a, b, theta=THETA):
+    return _lib().gamer_oracle_limiter(float(a), float(b), float(theta))
+
+
+def roe_flux(UL, UR, d, gamma):
+    """Roe flux along direction d between unrotated conserved states.
+    Returns (F[5], hlle_used)."""
+    UL, UR = _f64(UL), _f64(UR)
+    F = np.empty(5)
+    fb = _lib().gamer_oracle_roe_flux(_p(UL), _p(UR), int(d), gamma, _p(F))
+    return F, bool(fb)
+
+
+def roe_decompose(L, R, gamma):
+    """Roe decomposition of rotated states (normal = component 1).
+    Returns dict(avg=[u,v,w,H,a2,a], alpha[5], lam[5], K[5 wave, 5 comp])."""
+    L, R = _f64(L), _f64(R)
+    avg, alpha, lam, K = np.empty(6), np.empty(5), np.empty(5), np.empty((5, 5))
+    _lib().gamer_oracle_roe_decompose(_p(L), _p(R), gamma, _p(avg), _p(alpha), _p(lam), _p(K))
+    return dict(avg=avg, alpha=alpha, lam=lam, K=K)
+
+
+# --- per-group stages -------------------------------------------------------
+
+def group_prim(U, gamma):
+    U = _f64(U)
+    W = np.empty_like(U)
+    _lib().gamer_oracle_group_prim(_p(U), gamma, _p(W))
+    return W
+
+
+def group_slopes(W, theta=THETA):
+    W = _f64(W)
+    dW = np.empty((3, 5, 18, 18, 18))
+    _lib().gamer_oracle_group_slopes(_p(W), theta, _p(dW))
+    return dW
+
+
+def group_predict(U, W, dW, dt, dh, gamma):
+    U, W, dW = _f64(U), _f64(W), _f64(dW)
+    Ub = np.empty((3, 2, 5, 18, 18, 18))
+    n = _lib().gamer_oracle_group_predict(_p(U), _p(W), _p(dW), dt, dh, gamma, _p(Ub))
+    return Ub, int(n)
+
+
+def group_fluxes(Ub, gamma):
+    Ub = _f64(Ub)
+    Fl = np.empty((3, 5, 17, 16, 16))
+    n = _lib().gamer_oracle_group_fluxes(_p(Ub), gamma, _p(Fl))
+    return Fl, int(n)
+
+
+def group_update(U, Fl, dt, dh, want_planes=False):
+    U, Fl = _f64(U), _f64(Fl)
+    out = np.empty((5, 16, 16, 16))
+    planes = np.empty((3, 3, 5, 16, 16)) if want_planes else None
+    _lib().gamer_oracle_group_update(_p(U), _p(Fl), dt, dh, _p(out), _p(planes))
+    return (out, planes) if want_planes else out
+
+
+# --- batch entry points -----------------------------------------------------
+
+def hydro_solve(groups_in, dt, dh, gamma, theta=THETA, want_fluxes=False):
+    """One step on a batch.  Returns (groups_out, fluxes_or_None, (n_pred_fallback, n_hlle))."""
+    g = _f64(groups_in)
+    assert g.ndim == 5 and g.shape[1:] == (5, 20, 20, 20), g.shape
+    n = g.shape[0]
+    out = np.empty((n, 5, 16, 16, 16))
+    fl = np.empty((n, 3, 3, 5, 16, 16)) if want_fluxes else None
+    counts = (ctypes.c_longlong * 2)()
+    rc = _lib().gamer_oracle_hydro_solve(_p(g), n, dt, dh, gamma, theta, _p(fl), _p(out),
+                                         ctypes.cast(counts, _PLL))
+    if rc != 0:
+        raise ValueError("oracle hydro_solve rejected its arguments")
+    return out, fl, (int(counts[0]), int(counts[1]))
+
+
+def max_speed(groups, gamma):
+    g = _f64(groups)
+    return _lib().gamer_oracle_max_speed(_p(g), g.shape[0], gamma)
+
+
+def cfl_dt(groups, dh, gamma, cfl):
+    g = _f64(groups)
+    assert g.shape[1:] == (5, 16, 16, 16)
+    return _lib().gamer_oracle_cfl_dt(_p(g), g.shape[0], dh, gamma, cfl)
+
+
+def conserved_sums(groups, dh):
+    g = _f64(groups)
+    s = np.empty(5)
+    _lib().gamer_oracle_conserved_sums(_p(g), g.shape[0], dh, _p(s))
+    return s
+
+
+def pack_periodic(state, gx, gy, gz):
+    """state (G, 5, 16, 16, 16) with g = gx + Gx (gy + Gy gz)  ->  (G, 5, 20, 20, 20)."""
+    s = _f64(state)
+    assert s.shape == (gx * gy * gz, 5, 16, 16, 16)
+    out = np.empty((s.shape[0], 5, 20, 20, 20))
+    _lib().gamer_oracle_pack_periodic(_p(s), gx, gy, gz, _p(out))
+    return out
+
+
+def step_periodic(state, gx, gy, gz, dt, dh, gamma, theta=THETA):
+    """Ghost fill then one step of a uniform periodic grid held as groups."""
+    out, _, counts = hydro_solve(pack_periodic(state, gx, gy, gz), dt, dh, gamma, theta)
+    return out, counts
