@@ -1,0 +1,241 @@
+#!/usr/bin/env python3
+"""Throughput of the batched MUSCL-Hancock + Roe step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--dtype f32|f64|both]
+
+A step is one pass of the whole hot path over one batch of ghost-padded groups
+already resident in HBM: the fused solver launch (reconstruction, half-step
+prediction, Roe fluxes, full-step update, per-group sums and signal-speed
+maxima) followed by the reduction to the CFL time step and the conserved
+totals.  The time step is read on the device.  Workload: 256^3 periodic smooth
+flow (4096 groups of 16^3 + 2 ghost cells), seeded synthetic data.
+
+Prints one JSON line.  `value` is FP32 cell-updates/s; the FP64 figures sit
+under "fp64".  The roofline object is for the solver kernel of that precision:
+algorithmic flops per launch (a per-cell count of the method's arithmetic,
+times the cells per launch) over the kernel's mean duration from HIP events.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# ---- algorithmic work model (per group of 16^3 cells) ----------------------
+CELLS = 16 ** 3
+TOUCHED = 7360        # padded cells the five-point stencils read
+FACE_STATE = 5632     # interior + one ghost layer across each face
+FACES = 3 * 17 * 16 * 16
+# arithmetic operations (+ - * / sqrt) per unit of each stage
+FLOPS = {
+    "prim": (12, TOUCHED),
+    "slopes": (105, FACE_STATE),
+    "predictor": (290, FACE_STATE),
+    "roe": (219, FACES),
+    "update": (35, CELLS),
+    "cfl_sums": (24, CELLS),
+}
+FLOPS_PER_CELL = sum(f * n for f, n in FLOPS.values()) / CELLS
+
+
+def bytes_per_group(elem: int) -> int:
+    # read the padded group once, write the interior, 8 doubles of stats
+    return 5 * 20 ** 3 * elem + 5 * CELLS * elem + 8 * 8
+
+
+PEAK = {"f32": 157.3e12, "f64": 78.6e12}  # MI355X vector FP32 / FP64, FLOP/s
+HBM_PEAK = 8.0e12
+GAMMA = 5.0 / 3.0
+CFL = 0.5
+
+
+def read_traffic(kernel_tag: str):
+    """HBM bytes per launch from the committed counter summary, when it was taken
+    on the current kernel source; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "solve_kernel_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    src = open(os.path.join(ROOT, "paper_1007_3818_amd", "csrc", "solver.hip"), "rb").read()
+    digest = hashlib.sha256(src).hexdigest()[:16]
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("solver_sha256_16") != digest:
+        return None
+    v = vals.get(f"bytes_per_launch_{kernel_tag}")
+    return float(v) if v else None
+
+
+def bench_dtype(tag, padded, n_groups, dh, steps, warmup):
+    import torch
+    from paper_1007_3818_amd import hydro
+
+    dev = padded.device
+    out = torch.empty((n_groups, 5, 16, 16, 16), dtype=padded.dtype, device=dev)
+    stats = torch.empty((n_groups, 8), dtype=torch.float64, device=dev)
+    dh_dev = torch.full((1,), dh, dtype=torch.float64, device=dev)
+    dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
+    totals = torch.empty(7, dtype=torch.float64, device=dev)
+    # initial dt from the input's interior
+    hydro.group_stats(padded[:, :, 2:18, 2:18, 2:18].contiguous(), GAMMA, out=stats)
+    hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev, totals_out=totals)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        hydro.hydro_solve_batched(padded, None, dt_dev, dh_dev, GAMMA, out=out, group_stats=stats)
+        if ev is not None:
+            ev[1].record()
+        hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev, totals_out=totals)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record()
+    for i in range(steps):
+        step(evs[i])
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_step = t0.elapsed_time(t1) / steps
+    k_ms = sum(a.elapsed_time(b) for a, b in evs) / steps
+    cells = n_groups * CELLS
+    elem = padded.element_size()
+    flops = FLOPS_PER_CELL * cells
+    traffic = read_traffic(tag)
+    roof = {
+        "bound": "alu",
+        "achieved": flops / (k_ms * 1e-3) / 1e12,
+        "peak": PEAK[tag] / 1e12,
+        "unit": "TFLOP/s",
+        "frac": flops / (k_ms * 1e-3) / PEAK[tag],
+        "traffic": traffic,
+        "kernel": f"solve_kernel<{'float' if tag == 'f32' else 'double'}>",
+        "kernel_ms": k_ms,
+        "flops_per_cell": FLOPS_PER_CELL,
+        "algorithmic_bytes_per_cell": bytes_per_group(elem) / CELLS,
+        "hbm_achieved_GBps": bytes_per_group(elem) * n_groups / (k_ms * 1e-3) / 1e9,
+        "hbm_frac": bytes_per_group(elem) * n_groups / (k_ms * 1e-3) / HBM_PEAK,
+    }
+    tot = totals.cpu().tolist()
+    return {
+        "value": cells / (ms_step * 1e-3),
+        "ms_per_step": ms_step,
+        "wall_s": wall,
+        "solver_only_cell_updates_per_s": cells / (k_ms * 1e-3),
+        "roofline": roof,
+        "fallbacks": [int(tot[5]), int(tot[6])],
+        "dt": float(dt_dev.item()),
+    }
+
+
+def cpu_baseline(padded64_host, dh, dt):
+    """The FP64 oracle on host cores: all groups of the workload, one step, with
+    as many threads as the host offers (capped at 16)."""
+    import oracle
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+    oracle.set_threads(threads)
+    n = padded64_host.shape[0]
+    t = time.perf_counter()
+    oracle.hydro_solve(padded64_host, dt, dh, GAMMA)
+    el = time.perf_counter() - t
+    # one core on a subset, the paper's single-core comparison
+    oracle.set_threads(1)
+    sub = padded64_host[:128]
+    t = time.perf_counter()
+    oracle.hydro_solve(sub, dt, dh, GAMMA)
+    el1 = time.perf_counter() - t
+    return {
+        "value": n * CELLS / el,
+        "unit": "cell-updates/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"all {n} groups of the workload, one FP64 step, {threads} OpenMP threads ({el:.2f} s)",
+        "one_core": {"value": sub.shape[0] * CELLS / el1, "sample": f"first 128 groups, 1 thread ({el1:.2f} s)"},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--dtype", choices=["f32", "f64", "both"], default="both")
+    ap.add_argument("--n", type=int, default=256, help="cells per axis (multiple of 16)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (for counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
+                                   "note, not an implemented path", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_1007_3818_amd import hydro, workloads
+
+    dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    n = args.n
+    g = n // 16
+    state, dh = workloads.smooth_modes(n=n, device=dev)
+    n_groups = g ** 3
+    padded64 = hydro.pack_periodic(state, g, g, g)
+    res = {}
+    if args.dtype in ("f32", "both"):
+        padded32 = hydro.pack_periodic(state.float(), g, g, g)
+        res["f32"] = bench_dtype("f32", padded32, n_groups, dh, args.steps, args.warmup)
+        del padded32
+    if args.dtype in ("f64", "both"):
+        res["f64"] = bench_dtype("f64", padded64, n_groups, dh, args.steps, args.warmup)
+    main_tag = "f32" if "f32" in res else "f64"
+    m = res[main_tag]
+    line = {
+        "metric": "cell-updates/s, FP32 vs FP64 MUSCL-Hancock+Roe; % of HBM/VALU roofline",
+        "value": m["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_tag,
+        "data": "synthetic",
+        "config": {
+            "workload": f"smooth-mode flow {n}^3 periodic, {n_groups} groups of 16^3 + 2 ghost cells, gamma 5/3, CFL 0.5",
+            "groups": n_groups,
+            "cells": n_groups * CELLS,
+            "step": "batched solve (device dt) + CFL/totals reduce; padded input resident in HBM",
+        },
+        "roofline": m["roofline"],
+    }
+    for tag in ("f32", "f64"):
+        if tag in res:
+            line["fp32" if tag == "f32" else "fp64"] = {k: v for k, v in res[tag].items()}
+    if not args.no_cpu_baseline:
+        dt = res[main_tag]["dt"]
+        line["cpu_baseline"] = cpu_baseline(padded64.cpu().numpy(), dh, dt)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

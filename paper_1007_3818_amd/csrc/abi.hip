@@ -1,0 +1,275 @@
+// abi.hip -- the extern "C" entry points of include/gamer_hydro.h: argument
+// checks, per-thread stream and error state, library scratch, dispatch.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <mutex>
+
+#include "../../include/gamer_hydro.h"
+#include "internal.h"
+
+using namespace gamer;
+
+namespace {
+
+thread_local char g_err[512] = "";
+thread_local hipStream_t g_stream = nullptr;
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return GAMER_OK;
+    return fail(GAMER_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+// Library scratch: one growing device buffer per device, guarded by a mutex.
+// Calls that use it and overlap on different streams of one device race.
+struct Scratch {
+    std::mutex mu;
+    void *ptr[64] = {};
+    size_t size[64] = {};
+};
+Scratch g_scratch;
+
+int scratch(size_t bytes, void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(GAMER_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lock(g_scratch.mu);
+    if (g_scratch.size[dev] < bytes) {
+        if (g_scratch.ptr[dev]) {
+            // the old buffer may still be in use by queued work on any stream
+            if (hipDeviceSynchronize() != hipSuccess) return fail(GAMER_EHIP, "hipDeviceSynchronize");
+            (void)hipFree(g_scratch.ptr[dev]);
+            g_scratch.ptr[dev] = nullptr;
+            g_scratch.size[dev] = 0;
+        }
+        size_t want = bytes < 4096 ? 4096 : bytes;
+        if (hipMalloc(&g_scratch.ptr[dev], want) != hipSuccess) {
+            g_scratch.ptr[dev] = nullptr;
+            return fail(GAMER_ENOMEM, "could not allocate %zu bytes of scratch", want);
+        }
+        g_scratch.size[dev] = want;
+    }
+    *out = g_scratch.ptr[dev];
+    return GAMER_OK;
+}
+
+template <typename T>
+int solve_common(const T *in, int64_t n, const int8_t *level, const double *dt_dev,
+                 const double *dh_dev, int n_levels, double dt, double dh, double gamma,
+                 T *fluxes, T *out, double *stats, const gamer_opts *opts) {
+    g_err[0] = 0;
+    if (n < 0) return fail(GAMER_EINVAL, "n_groups < 0");
+    if (!(isfinite(gamma) && gamma > 1.0)) return fail(GAMER_EINVAL, "gamma must be > 1");
+    const double theta = opts ? opts->theta : 1.5;
+    if (!(theta >= 1.0 && theta <= 2.0)) return fail(GAMER_EINVAL, "theta must lie in [1, 2]");
+    if (!dt_dev && (!finite_pos(dt) || !finite_pos(dh)))
+        return fail(GAMER_EINVAL, "dt and dh must be finite and positive");
+    if (n == 0) return GAMER_OK;
+    if (!in || !out) return fail(GAMER_EINVAL, "NULL groups_in or groups_out");
+    if (dt_dev && !dh_dev) return fail(GAMER_EINVAL, "NULL dh_dev");
+    if (dt_dev && (n_levels < 1 || n_levels > GAMER_MAX_LEVELS))
+        return fail(GAMER_EINVAL, "n_levels must lie in [1, %d]", GAMER_MAX_LEVELS);
+    SolveParams<T> p;
+    p.in = in;
+    p.out = out;
+    p.flux = fluxes;
+    p.stats = stats;
+    p.level = level;
+    p.dt_dev = dt_dev;
+    p.dh_dev = dh_dev;
+    p.dt = dt;
+    p.dh = dh;
+    p.gamma = gamma;
+    p.theta = theta;
+    p.n_groups = n;
+    return check_hip(launch_solve<T>(p, g_stream), "solver launch");
+}
+
+template <typename T>
+int cfl_common(const T *groups, int64_t n, double dh, double gamma, double cfl, double *dt_out,
+               int dt_dev) {
+    g_err[0] = 0;
+    if (n < 0) return fail(GAMER_EINVAL, "n_groups < 0");
+    if (!finite_pos(dh) || !finite_pos(cfl) || !(isfinite(gamma) && gamma > 1.0))
+        return fail(GAMER_EINVAL, "dh and cfl must be finite and positive, gamma > 1");
+    if (n == 0) return GAMER_OK;
+    if (!dt_out) return fail(GAMER_EINVAL, "NULL dt_out");
+    if (!groups) return fail(GAMER_EINVAL, "NULL groups");
+    void *buf = nullptr;
+    int rc = scratch(size_t(n) * NSTAT * sizeof(double) + 64, &buf);
+    if (rc) return rc;
+    double *stats = static_cast<double *>(buf);
+    double *dt_tmp = stats + size_t(n) * NSTAT;
+    if ((rc = check_hip(launch_group_stats<T>(groups, n, gamma, stats, g_stream), "stats launch")))
+        return rc;
+    double *dst = dt_dev ? dt_out : dt_tmp;
+    if ((rc = check_hip(launch_reduce(stats, n, nullptr, nullptr, dh, 1, cfl, dst, nullptr, g_stream),
+                        "reduce launch")))
+        return rc;
+    if (!dt_dev) {
+        if ((rc = check_hip(hipMemcpyAsync(dt_out, dt_tmp, sizeof(double), hipMemcpyDeviceToHost,
+                                           g_stream), "copy dt")))
+            return rc;
+        return check_hip(hipStreamSynchronize(g_stream), "stream sync");
+    }
+    return GAMER_OK;
+}
+
+template <typename T>
+int sums_common(const T *groups, int64_t n, double dh, double *sums5, int is_dev) {
+    g_err[0] = 0;
+    if (n < 0) return fail(GAMER_EINVAL, "n_groups < 0");
+    if (!finite_pos(dh)) return fail(GAMER_EINVAL, "dh must be finite and positive");
+    if (n == 0) return GAMER_OK;
+    if (!sums5) return fail(GAMER_EINVAL, "NULL sums5_out");
+    if (!groups) return fail(GAMER_EINVAL, "NULL groups");
+    void *buf = nullptr;
+    int rc = scratch(size_t(n) * NSTAT * sizeof(double) + 64, &buf);
+    if (rc) return rc;
+    double *stats = static_cast<double *>(buf);
+    double *tot = stats + size_t(n) * NSTAT;  // 7 doubles (56 B) fit in the 64 B tail
+    // gamma only enters stat 5, which the totals ignore
+    if ((rc = check_hip(launch_group_stats<T>(groups, n, 2.0, stats, g_stream), "stats launch")))
+        return rc;
+    if ((rc = check_hip(launch_reduce(stats, n, nullptr, nullptr, dh, 1, 1.0, nullptr, tot, g_stream),
+                        "reduce launch")))
+        return rc;
+    if (is_dev)
+        return check_hip(hipMemcpyAsync(sums5, tot, 5 * sizeof(double), hipMemcpyDeviceToDevice,
+                                        g_stream), "copy sums");
+    if ((rc = check_hip(hipMemcpyAsync(sums5, tot, 5 * sizeof(double), hipMemcpyDeviceToHost,
+                                       g_stream), "copy sums")))
+        return rc;
+    return check_hip(hipStreamSynchronize(g_stream), "stream sync");
+}
+
+template <typename T>
+int pack_common(const T *state, int gx, int gy, int gz, T *padded) {
+    g_err[0] = 0;
+    if (gx < 1 || gy < 1 || gz < 1) return fail(GAMER_EINVAL, "gx, gy, gz must be >= 1");
+    if (int64_t(gx) * NI > (1 << 28) || int64_t(gy) * NI > (1 << 28) || int64_t(gz) * NI > (1 << 28))
+        return fail(GAMER_EINVAL, "grid too large");
+    if (!state || !padded) return fail(GAMER_EINVAL, "NULL state or padded");
+    return check_hip(launch_pack_periodic<T>(state, gx, gy, gz, padded, g_stream), "pack launch");
+}
+
+template <typename T>
+int stats_common(const T *groups, int64_t n, double gamma, double *stats) {
+    g_err[0] = 0;
+    if (n < 0) return fail(GAMER_EINVAL, "n_groups < 0");
+    if (!(isfinite(gamma) && gamma > 1.0)) return fail(GAMER_EINVAL, "gamma must be > 1");
+    if (n == 0) return GAMER_OK;
+    if (!groups || !stats) return fail(GAMER_EINVAL, "NULL groups or group_stats");
+    return check_hip(launch_group_stats<T>(groups, n, gamma, stats, g_stream), "stats launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+int gamer_version(void) { return 100; }
+
+int gamer_set_stream(void *hip_stream) {
+    g_stream = static_cast<hipStream_t>(hip_stream);
+    return GAMER_OK;
+}
+
+void *gamer_get_stream(void) { return g_stream; }
+
+const char *gamer_last_error(void) { return g_err; }
+
+int gamer_hydro_solve(const double *groups_in, int64_t n_groups, double dt, double dh,
+                      double gamma, double *fluxes_out, double *groups_out) {
+    return solve_common<double>(groups_in, n_groups, nullptr, nullptr, nullptr, 1, dt, dh, gamma,
+                                fluxes_out, groups_out, nullptr, nullptr);
+}
+
+int gamer_hydro_solve_f32(const float *groups_in, int64_t n_groups, double dt, double dh,
+                          double gamma, float *fluxes_out, float *groups_out) {
+    return solve_common<float>(groups_in, n_groups, nullptr, nullptr, nullptr, 1, dt, dh, gamma,
+                               fluxes_out, groups_out, nullptr, nullptr);
+}
+
+int gamer_hydro_solve_batched(const double *groups_in, int64_t n_groups, const int8_t *level,
+                              const double *dt_dev, const double *dh_dev, int n_levels,
+                              double gamma, double *fluxes_out, double *groups_out,
+                              double *group_stats, const gamer_opts *opts) {
+    if (!dt_dev && n_groups > 0) return fail(GAMER_EINVAL, "NULL dt_dev");
+    return solve_common<double>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, 0.0, 0.0,
+                                gamma, fluxes_out, groups_out, group_stats, opts);
+}
+
+int gamer_hydro_solve_batched_f32(const float *groups_in, int64_t n_groups, const int8_t *level,
+                                  const double *dt_dev, const double *dh_dev, int n_levels,
+                                  double gamma, float *fluxes_out, float *groups_out,
+                                  double *group_stats, const gamer_opts *opts) {
+    if (!dt_dev && n_groups > 0) return fail(GAMER_EINVAL, "NULL dt_dev");
+    return solve_common<float>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, 0.0, 0.0,
+                               gamma, fluxes_out, groups_out, group_stats, opts);
+}
+
+int gamer_step_reduce(const double *group_stats, int64_t n_groups, const int8_t *level,
+                      const double *dh_dev, int n_levels, double cfl, double *dt_dev_out,
+                      double *totals_dev_out) {
+    g_err[0] = 0;
+    if (n_groups < 0) return fail(GAMER_EINVAL, "n_groups < 0");
+    if (!finite_pos(cfl)) return fail(GAMER_EINVAL, "cfl must be finite and positive");
+    if (n_levels < 1 || n_levels > GAMER_MAX_LEVELS)
+        return fail(GAMER_EINVAL, "n_levels must lie in [1, %d]", GAMER_MAX_LEVELS);
+    if (!dh_dev) return fail(GAMER_EINVAL, "NULL dh_dev");
+    if (n_groups > 0 && !group_stats) return fail(GAMER_EINVAL, "NULL group_stats");
+    if (!dt_dev_out && !totals_dev_out) return GAMER_OK;
+    return check_hip(launch_reduce(group_stats, n_groups, level, dh_dev, 0.0, n_levels, cfl,
+                                   dt_dev_out, totals_dev_out, g_stream),
+                     "reduce launch");
+}
+
+int gamer_group_stats(const double *groups, int64_t n_groups, double gamma, double *group_stats) {
+    return stats_common<double>(groups, n_groups, gamma, group_stats);
+}
+
+int gamer_group_stats_f32(const float *groups, int64_t n_groups, double gamma,
+                          double *group_stats) {
+    return stats_common<float>(groups, n_groups, gamma, group_stats);
+}
+
+int gamer_cfl_dt(const double *groups, int64_t n_groups, double dh, double gamma, double cfl,
+                 double *dt_out, int dt_out_is_device) {
+    return cfl_common<double>(groups, n_groups, dh, gamma, cfl, dt_out, dt_out_is_device);
+}
+
+int gamer_cfl_dt_f32(const float *groups, int64_t n_groups, double dh, double gamma, double cfl,
+                     double *dt_out, int dt_out_is_device) {
+    return cfl_common<float>(groups, n_groups, dh, gamma, cfl, dt_out, dt_out_is_device);
+}
+
+int gamer_conserved_sums(const double *groups, int64_t n_groups, double dh, double *sums5_out,
+                         int is_device) {
+    return sums_common<double>(groups, n_groups, dh, sums5_out, is_device);
+}
+
+int gamer_conserved_sums_f32(const float *groups, int64_t n_groups, double dh,
+                             double *sums5_out, int is_device) {
+    return sums_common<float>(groups, n_groups, dh, sums5_out, is_device);
+}
+
+int gamer_pack_periodic(const double *state, int gx, int gy, int gz, double *padded) {
+    return pack_common<double>(state, gx, gy, gz, padded);
+}
+
+int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *padded) {
+    return pack_common<float>(state, gx, gy, gz, padded);
+}
+
+}  // extern "C"

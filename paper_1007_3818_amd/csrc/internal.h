@@ -1,0 +1,53 @@
+// internal.h -- declarations shared by the translation units of libgamer_hydro.so.
+// Not installed; the public interface is include/gamer_hydro.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gamer {
+
+// Patch-group geometry: 16^3 interior cells, two ghost cells per side (the
+// five-point stencil of MUSCL-Hancock), five conserved variables.
+constexpr int NI = 16;
+constexpr int NG = 2;
+constexpr int NP = NI + 2 * NG;               // 20
+constexpr int NPL = NP * NP;                  // cells in one padded z-plane
+constexpr int NV = 5;
+constexpr int64_t GIN = int64_t(NV) * NP * NP * NP;    // values per padded group
+constexpr int64_t GOUT = int64_t(NV) * NI * NI * NI;   // values per interior group
+constexpr int64_t GFLX = int64_t(3) * 3 * NV * NI * NI;  // values per flux-plane set
+constexpr int NSTAT = 8;                      // doubles of group stats
+constexpr int MAX_LEVELS = 32;
+
+template <typename T>
+struct SolveParams {
+    const T *in;          // [n][5][20][20][20]
+    T *out;               // [n][5][16][16][16]
+    T *flux;              // [n][3][3][5][16][16] or nullptr
+    double *stats;        // [n][8] or nullptr
+    const int8_t *level;  // [n] or nullptr
+    const double *dt_dev; // [n_levels] or nullptr (then dt, dh below)
+    const double *dh_dev;
+    double dt, dh;
+    double gamma, theta;
+    int64_t n_groups;
+};
+
+template <typename T>
+hipError_t launch_solve(const SolveParams<T> &p, hipStream_t s);
+
+template <typename T>
+hipError_t launch_pack_periodic(const T *state, int gx, int gy, int gz, T *padded, hipStream_t s);
+
+template <typename T>
+hipError_t launch_group_stats(const T *groups, int64_t n, double gamma, double *stats,
+                              hipStream_t s);
+
+// dt_out[L] and totals_out[7] from group stats; dh_dev may be nullptr (then the
+// scalar dh applies to every group, and level must be nullptr too).
+hipError_t launch_reduce(const double *stats, int64_t n, const int8_t *level, const double *dh_dev,
+                         double dh, int n_levels, double cfl, double *dt_out, double *totals_out,
+                         hipStream_t s);
+
+}  // namespace gamer

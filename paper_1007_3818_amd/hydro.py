@@ -1,0 +1,163 @@
+"""Torch-tensor front end of the C ABI (device memory and streams only).
+
+Each function checks shapes, dtypes and devices, sets the library's stream to
+torch's current stream and calls the entry point of the same name in
+include/gamer_hydro.h.  All arithmetic happens in the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _native
+
+NI, NP, NV = 16, 20, 5
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    _native.check(_native.lib().gamer_set_stream(
+        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+
+def _need(t, shape_tail, dtype, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape[1:]) != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape (n, {', '.join(map(str, shape_tail))}), got {tuple(t.shape)}")
+
+
+def _f32(dtype):
+    if dtype == torch.float32:
+        return True
+    if dtype == torch.float64:
+        return False
+    raise TypeError(f"unsupported dtype {dtype}")
+
+
+def hydro_solve(groups_in, dt, dh, gamma, out=None, fluxes_out=None):
+    """One MUSCL-Hancock + Roe step of every padded group (same dt, dh)."""
+    f32 = _f32(groups_in.dtype)
+    _need(groups_in, (NV, NP, NP, NP), groups_in.dtype, "groups_in")
+    n = groups_in.shape[0]
+    if out is None:
+        out = torch.empty((n, NV, NI, NI, NI), dtype=groups_in.dtype, device=groups_in.device)
+    _need(out, (NV, NI, NI, NI), groups_in.dtype, "out")
+    if fluxes_out is not None:
+        _need(fluxes_out, (3, 3, NV, NI, NI), groups_in.dtype, "fluxes_out")
+    _stream()
+    fn = _native.lib().gamer_hydro_solve_f32 if f32 else _native.lib().gamer_hydro_solve
+    _native.check(fn(_ptr(groups_in), n, float(dt), float(dh), float(gamma), _ptr(fluxes_out), _ptr(out)))
+    return out
+
+
+def hydro_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxes_out=None,
+                        group_stats=None, theta=None):
+    """One persistent launch over groups of uneven level; dt and dh read on the device."""
+    f32 = _f32(groups_in.dtype)
+    _need(groups_in, (NV, NP, NP, NP), groups_in.dtype, "groups_in")
+    n = groups_in.shape[0]
+    if out is None:
+        out = torch.empty((n, NV, NI, NI, NI), dtype=groups_in.dtype, device=groups_in.device)
+    _need(out, (NV, NI, NI, NI), groups_in.dtype, "out")
+    if fluxes_out is not None:
+        _need(fluxes_out, (3, 3, NV, NI, NI), groups_in.dtype, "fluxes_out")
+    if group_stats is not None:
+        _need(group_stats, (8,), torch.float64, "group_stats")
+    if level is not None:
+        if level.dtype != torch.int8 or not level.is_cuda or level.numel() != n:
+            raise ValueError("level must be a GPU int8 tensor with one entry per group")
+    for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
+        if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 1:
+            raise ValueError(f"{nm} must be a 1-D GPU float64 tensor")
+    n_levels = dt_dev.numel()
+    opts = _native.GamerOpts(theta) if theta is not None else None
+    _stream()
+    fn = (_native.lib().gamer_hydro_solve_batched_f32 if f32
+          else _native.lib().gamer_hydro_solve_batched)
+    _native.check(fn(_ptr(groups_in), n, _ptr(level), _ptr(dt_dev), _ptr(dh_dev), n_levels,
+                     float(gamma), _ptr(fluxes_out), _ptr(out), _ptr(group_stats),
+                     ctypes.byref(opts) if opts is not None else None))
+    return out
+
+
+def step_reduce(group_stats, level, dh_dev, cfl, dt_out=None, totals_out=None):
+    """Per-level dt and conserved totals (+ fallback counts) from group stats, on the device."""
+    _need(group_stats, (8,), torch.float64, "group_stats")
+    n = group_stats.shape[0]
+    n_levels = dh_dev.numel()
+    dev = group_stats.device
+    if dt_out is None:
+        dt_out = torch.empty(n_levels, dtype=torch.float64, device=dev)
+    if totals_out is None:
+        totals_out = torch.empty(7, dtype=torch.float64, device=dev)
+    _stream()
+    _native.check(_native.lib().gamer_step_reduce(_ptr(group_stats), n, _ptr(level), _ptr(dh_dev),
+                                                  n_levels, float(cfl), _ptr(dt_out), _ptr(totals_out)))
+    return dt_out, totals_out
+
+
+def group_stats(groups, gamma, out=None):
+    f32 = _f32(groups.dtype)
+    _need(groups, (NV, NI, NI, NI), groups.dtype, "groups")
+    n = groups.shape[0]
+    if out is None:
+        out = torch.empty((n, 8), dtype=torch.float64, device=groups.device)
+    _stream()
+    fn = _native.lib().gamer_group_stats_f32 if f32 else _native.lib().gamer_group_stats
+    _native.check(fn(_ptr(groups), n, float(gamma), _ptr(out)))
+    return out
+
+
+def cfl_dt(groups, dh, gamma, cfl, device_out=False):
+    """dt = cfl dh / max(|u|+|v|+|w|+3 c_s); a float, or a 1-element GPU tensor."""
+    f32 = _f32(groups.dtype)
+    _need(groups, (NV, NI, NI, NI), groups.dtype, "groups")
+    _stream()
+    fn = _native.lib().gamer_cfl_dt_f32 if f32 else _native.lib().gamer_cfl_dt
+    if device_out:
+        out = torch.empty(1, dtype=torch.float64, device=groups.device)
+        _native.check(fn(_ptr(groups), groups.shape[0], float(dh), float(gamma), float(cfl), _ptr(out), 1))
+        return out
+    host = ctypes.c_double(0.0)
+    _native.check(fn(_ptr(groups), groups.shape[0], float(dh), float(gamma), float(cfl),
+                     ctypes.cast(ctypes.byref(host), ctypes.c_void_p), 0))
+    return host.value
+
+
+def conserved_sums(groups, dh, device_out=False):
+    f32 = _f32(groups.dtype)
+    _need(groups, (NV, NI, NI, NI), groups.dtype, "groups")
+    _stream()
+    fn = _native.lib().gamer_conserved_sums_f32 if f32 else _native.lib().gamer_conserved_sums
+    if device_out:
+        out = torch.empty(5, dtype=torch.float64, device=groups.device)
+        _native.check(fn(_ptr(groups), groups.shape[0], float(dh), _ptr(out), 1))
+        return out
+    host = (ctypes.c_double * 5)()
+    _native.check(fn(_ptr(groups), groups.shape[0], float(dh), ctypes.cast(host, ctypes.c_void_p), 0))
+    return list(host)
+
+
+def pack_periodic(state, gx, gy, gz, out=None):
+    f32 = _f32(state.dtype)
+    _need(state, (NV, NI, NI, NI), state.dtype, "state")
+    if state.shape[0] != gx * gy * gz:
+        raise ValueError("state must hold gx*gy*gz groups")
+    if out is None:
+        out = torch.empty((state.shape[0], NV, NP, NP, NP), dtype=state.dtype, device=state.device)
+    _need(out, (NV, NP, NP, NP), state.dtype, "out")
+    _stream()
+    fn = _native.lib().gamer_pack_periodic_f32 if f32 else _native.lib().gamer_pack_periodic
+    _native.check(fn(_ptr(state), int(gx), int(gy), int(gz), _ptr(out)))
+    return out

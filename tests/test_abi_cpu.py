@@ -1,0 +1,120 @@
+"""Host-side checks of the C ABI (no GPU needed): the library builds and loads,
+exports every symbol the header declares, and rejects bad arguments before it
+touches the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1007_3818_amd import _native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gamer_hydro.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gamer_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_native.LIB_PATH):
+        from paper_1007_3818_amd import build
+        build.build()
+    return _native.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) == 17
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _native.SIGNATURES, n
+    assert set(_native.SIGNATURES) == set(names)
+
+
+def test_opts_struct_layout():
+    # gamer_opts holds one double
+    assert ctypes.sizeof(_native.GamerOpts) == 8
+
+
+def test_version(lib):
+    assert lib.gamer_version() >= 100
+
+
+def _rc(fn, *args):
+    return fn(*args)
+
+
+P = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+
+
+def test_solve_argument_errors(lib):
+    f = lib.gamer_hydro_solve
+    assert f(None, 4, 0.1, 0.1, 1.4, None, P) == _native.GAMER_EINVAL
+    assert b"NULL" in lib.gamer_last_error()
+    assert f(P, 4, 0.1, 0.1, 1.4, None, None) == _native.GAMER_EINVAL
+    assert f(P, -1, 0.1, 0.1, 1.4, None, P) == _native.GAMER_EINVAL
+    assert f(P, 4, 0.0, 0.1, 1.4, None, P) == _native.GAMER_EINVAL
+    assert f(P, 4, float("nan"), 0.1, 1.4, None, P) == _native.GAMER_EINVAL
+    assert f(P, 4, 0.1, -1.0, 1.4, None, P) == _native.GAMER_EINVAL
+    assert f(P, 4, 0.1, 0.1, 1.0, None, P) == _native.GAMER_EINVAL
+    assert f(P, 4, 0.1, 0.1, float("inf"), None, P) == _native.GAMER_EINVAL
+    # zero groups: a successful no-op, even with NULL arrays
+    assert f(None, 0, 0.1, 0.1, 1.4, None, None) == _native.GAMER_OK
+    assert lib.gamer_hydro_solve_f32(None, 0, 0.1, 0.1, 1.4, None, None) == _native.GAMER_OK
+
+
+def test_batched_argument_errors(lib):
+    f = lib.gamer_hydro_solve_batched
+    assert f(P, 4, None, None, P, 1, 1.4, None, P, None, None) == _native.GAMER_EINVAL  # no dt_dev
+    assert f(P, 4, None, P, None, 1, 1.4, None, P, None, None) == _native.GAMER_EINVAL  # no dh_dev
+    assert f(P, 4, None, P, P, 0, 1.4, None, P, None, None) == _native.GAMER_EINVAL
+    assert f(P, 4, None, P, P, 33, 1.4, None, P, None, None) == _native.GAMER_EINVAL
+    bad = _native.GamerOpts(2.5)
+    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+    bad = _native.GamerOpts(0.5)
+    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+
+
+def test_other_entry_point_errors(lib):
+    assert lib.gamer_step_reduce(P, 4, None, P, 1, 0.0, P, None) == _native.GAMER_EINVAL
+    assert lib.gamer_step_reduce(P, 4, None, None, 1, 0.5, P, None) == _native.GAMER_EINVAL
+    assert lib.gamer_step_reduce(P, 4, None, P, 40, 0.5, P, None) == _native.GAMER_EINVAL
+    assert lib.gamer_step_reduce(None, 4, None, P, 1, 0.5, P, None) == _native.GAMER_EINVAL
+    assert lib.gamer_cfl_dt(P, 4, 0.0, 1.4, 0.5, P, 1) == _native.GAMER_EINVAL
+    assert lib.gamer_cfl_dt(P, 4, 0.1, 1.4, -0.5, P, 1) == _native.GAMER_EINVAL
+    assert lib.gamer_cfl_dt(P, 4, 0.1, 1.4, 0.5, None, 1) == _native.GAMER_EINVAL
+    assert lib.gamer_cfl_dt(None, 4, 0.1, 1.4, 0.5, P, 1) == _native.GAMER_EINVAL
+    assert lib.gamer_cfl_dt(None, 0, 0.1, 1.4, 0.5, None, 0) == _native.GAMER_OK
+    assert lib.gamer_conserved_sums(P, 4, 0.0, P, 1) == _native.GAMER_EINVAL
+    assert lib.gamer_conserved_sums(P, 4, 0.1, None, 1) == _native.GAMER_EINVAL
+    assert lib.gamer_group_stats(P, 4, 1.0, P) == _native.GAMER_EINVAL
+    assert lib.gamer_group_stats(None, 4, 1.4, P) == _native.GAMER_EINVAL
+    assert lib.gamer_pack_periodic(P, 0, 1, 1, P) == _native.GAMER_EINVAL
+    assert lib.gamer_pack_periodic(None, 1, 1, 1, P) == _native.GAMER_EINVAL
+    assert lib.gamer_pack_periodic_f32(P, 1, 1, 1, None) == _native.GAMER_EINVAL
+
+
+def test_stream_is_per_thread_state(lib):
+    import threading
+    assert lib.gamer_set_stream(ctypes.c_void_p(0x1234)) == 0
+    seen = []
+    t = threading.Thread(target=lambda: seen.append(lib.gamer_get_stream()))
+    t.start()
+    t.join()
+    assert lib.gamer_get_stream() == 0x1234
+    assert seen == [None]
+    lib.gamer_set_stream(None)
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+    from paper_1007_3818_amd import hydro
+    with pytest.raises(ValueError):
+        hydro.hydro_solve(torch.zeros((1, 5, 20, 20, 20), dtype=torch.float64), 0.1, 0.1, 1.4)
+    with pytest.raises(TypeError):
+        hydro.hydro_solve(torch.zeros((1, 5, 20, 20, 20), dtype=torch.float16), 0.1, 0.1, 1.4)

@@ -1,0 +1,268 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Tolerances (stated per test):
+  FP64: |gpu - oracle| <= 1e-12 (|oracle| + s_v) per value, s_v = max |oracle| of
+        variable v over the batch (a per-variable scale for near-zero momenta).
+  FP32: the oracle runs on the float32-rounded input converted to double;
+        smooth flow |gpu - oracle| <= 1e-5 (|oracle| + s_v); shocked runs report L1.
+  Integers (fallback counts) and the periodic ghost fill: exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle_driver import run_periodic
+from paper_1007_3818_amd import hydro, workloads as W
+from paper_1007_3818_amd.stepper import PeriodicGrid
+
+pytestmark = pytest.mark.gpu
+G53 = 5.0 / 3.0
+
+
+def close(gpu, ora, rtol, what=""):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ora = np.asarray(ora, dtype=np.float64)
+    assert gpu.shape == ora.shape
+    # per-variable scale along the field axis (axis 1 for (n,5,...) arrays)
+    axes = tuple(i for i in range(ora.ndim) if i != 1)
+    s = np.abs(ora).max(axis=axes, keepdims=True)
+    denom = np.abs(ora) + s
+    # a variable that is exactly zero everywhere (e.g. transverse momentum of a
+    # 1D problem) must come out exactly zero
+    err = np.where(denom > 0, np.abs(gpu - ora) / np.where(denom > 0, denom, 1.0),
+                   np.where(gpu == ora, 0.0, np.inf))
+    worst = float(err.max()) if err.size else 0.0
+    assert worst <= rtol, f"{what}: max relative error {worst:.3e} > {rtol:.1e}"
+    return worst
+
+
+def padded_pair(state64, gx, gy, gz, dtype, dev):
+    """GPU-packed input in `dtype` and the oracle's own packed input of the same
+    (rounded) state in float64."""
+    st = state64.to(dtype)
+    gpu_pad = hydro.pack_periodic(st.to(dev), gx, gy, gz)
+    ora_pad = oracle.pack_periodic(st.double().numpy(), gx, gy, gz)
+    return gpu_pad, ora_pad
+
+
+# ------------------------------------------------------------------ ghost fill
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_pack_periodic_bitwise(gpu, dtype):
+    r = np.random.default_rng(11)
+    gx, gy, gz = 3, 2, 2
+    st = torch.from_numpy(r.standard_normal((gx * gy * gz, 5, 16, 16, 16)))
+    gp, op = padded_pair(st, gx, gy, gz, dtype, gpu)
+    assert np.array_equal(gp.cpu().double().numpy(), op)
+
+
+# ------------------------------------------------------------------ exact cases
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_uniform_state_bitwise(gpu, dtype):
+    W_ = [0.7, 0.3, -1.1, 2.0, 1.9]
+    U = torch.tensor(oracle.cons_from_prim(W_, G53)).to(dtype)
+    pad = U[None, :, None, None, None].expand(6, 5, 20, 20, 20).contiguous().to(gpu)
+    flux = torch.empty((6, 3, 3, 5, 16, 16), dtype=dtype, device=gpu)
+    out = hydro.hydro_solve(pad, 0.01, 0.1, G53, fluxes_out=flux)
+    torch.cuda.synchronize()
+    assert torch.equal(out.cpu(), pad[:, :, 2:18, 2:18, 2:18].cpu())
+
+
+def test_zero_groups_is_noop(gpu):
+    pad = torch.empty((0, 5, 20, 20, 20), dtype=torch.float64, device=gpu)
+    out = hydro.hydro_solve(pad, 0.01, 0.1, G53)
+    assert out.shape[0] == 0
+
+
+# ------------------------------------------------------------------ one-step parity
+
+def _cases():
+    yield "sod", W.sod_x(), (2, 2, 2)
+    yield "smooth48", W.smooth_modes(n=48), (3, 3, 3)
+    yield "cosmo32", W.cosmo_like(n=32), (2, 2, 2)
+
+
+@pytest.mark.parametrize("name", ["sod", "smooth48", "cosmo32"])
+def test_one_step_fp64_parity(gpu, name):
+    (st, dh), (gx, gy, gz) = next((c[1], c[2]) for c in _cases() if c[0] == name)
+    gp, op = padded_pair(st, gx, gy, gz, torch.float64, gpu)
+    dt = oracle.cfl_dt(st.numpy(), dh, G53, 0.5)
+    ora, ofl, ocnt = oracle.hydro_solve(op, dt, dh, G53, want_fluxes=True)
+    flux = torch.empty((gp.shape[0], 3, 3, 5, 16, 16), dtype=torch.float64, device=gpu)
+    out = hydro.hydro_solve(gp, dt, dh, G53, fluxes_out=flux)
+    torch.cuda.synchronize()
+    close(out.cpu().numpy(), ora, 1e-12, f"{name} state")
+    close(flux.cpu().numpy().transpose(0, 3, 1, 2, 4, 5), ofl.transpose(0, 3, 1, 2, 4, 5), 1e-12,
+          f"{name} fluxes")
+
+
+@pytest.mark.parametrize("name", ["sod", "smooth48", "cosmo32"])
+def test_fallback_counts_match(gpu, name):
+    """Predictor and HLLE fallback counts (integers) equal the oracle's."""
+    (st, dh), (gx, gy, gz) = next((c[1], c[2]) for c in _cases() if c[0] == name)
+    gp, op = padded_pair(st, gx, gy, gz, torch.float64, gpu)
+    dt = oracle.cfl_dt(st.numpy(), dh, G53, 0.5)
+    _, _, ocnt = oracle.hydro_solve(op, dt, dh, G53)
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device=gpu)
+    dh_dev = torch.tensor([dh], dtype=torch.float64, device=gpu)
+    stats = torch.empty((gp.shape[0], 8), dtype=torch.float64, device=gpu)
+    hydro.hydro_solve_batched(gp, None, dt_dev, dh_dev, G53, group_stats=stats)
+    _, tot = hydro.step_reduce(stats, None, dh_dev, 0.5)
+    t = tot.cpu().numpy()
+    assert (int(t[5]), int(t[6])) == ocnt
+
+
+@pytest.mark.parametrize("name", ["smooth48", "cosmo32"])
+def test_one_step_fp32_parity(gpu, name):
+    (st, dh), (gx, gy, gz) = next((c[1], c[2]) for c in _cases() if c[0] == name)
+    gp, op = padded_pair(st, gx, gy, gz, torch.float32, gpu)
+    dt = oracle.cfl_dt(st.float().double().numpy(), dh, G53, 0.5)
+    ora, ofl, _ = oracle.hydro_solve(op, dt, dh, G53, want_fluxes=True)
+    flux = torch.empty((gp.shape[0], 3, 3, 5, 16, 16), dtype=torch.float32, device=gpu)
+    out = hydro.hydro_solve(gp, dt, dh, G53, fluxes_out=flux)
+    torch.cuda.synchronize()
+    if name == "smooth48":
+        close(out.cpu().numpy(), ora, 1e-5, "fp32 smooth state")
+        close(flux.cpu().numpy().transpose(0, 3, 1, 2, 4, 5), ofl.transpose(0, 3, 1, 2, 4, 5),
+              1e-4, "fp32 smooth fluxes")
+    else:
+        # Mach-10 log-normal flow: L1 of the relative difference per variable
+        o = out.cpu().double().numpy()
+        l1 = np.abs(o - ora).sum(axis=(0, 2, 3, 4)) / np.abs(ora).sum(axis=(0, 2, 3, 4))
+        assert np.all(l1 < 1e-5), l1
+
+
+def test_sod_fp32_l1(gpu):
+    st, dh = W.sod_x()
+    gp, op = padded_pair(st, 2, 2, 2, torch.float32, gpu)
+    dt = oracle.cfl_dt(st.numpy(), dh, G53, 0.5)
+    ora, _, _ = oracle.hydro_solve(op, dt, dh, G53)
+    out = hydro.hydro_solve(gp, dt, dh, G53)
+    l1 = np.abs(out.cpu().double().numpy() - ora).sum(axis=(0, 2, 3, 4)) / np.abs(ora).sum(axis=(0, 2, 3, 4)).clip(1e-300)
+    assert np.all(l1[[0, 1, 4]] < 1e-6), l1
+
+
+# ------------------------------------------------------------------ multi-step
+
+def test_sod_ten_steps_fp64(gpu):
+    """Workload 1: ten steps at CFL 0.5 with the device-resident time step."""
+    st, dh = W.sod_x()
+    ora, t_ora, _, counts = run_periodic(st.numpy(), 2, 2, 2, dh, G53, 0.5, steps=10)
+    assert counts == (0, 0)
+    grid = PeriodicGrid(st.to(gpu), 2, 2, 2, dh, G53, 0.5)
+    grid.step(10)
+    torch.cuda.synchronize()
+    close(grid.current.cpu().numpy(), ora, 1e-12, "sod 10 steps")
+    assert grid.time() == pytest.approx(t_ora, rel=1e-13)
+
+
+def test_smooth_twenty_steps_fp64_and_graph(gpu):
+    """20 steps of smooth flow, eager and replayed from a captured HIP graph:
+    both match the oracle, and each other bitwise."""
+    st, dh = W.smooth_modes(n=32)
+    ora, t_ora, _, counts = run_periodic(st.numpy(), 2, 2, 2, dh, G53, 0.5, steps=20)
+    eager = PeriodicGrid(st.to(gpu), 2, 2, 2, dh, G53, 0.5)
+    eager.step(20)
+    graph = PeriodicGrid(st.to(gpu), 2, 2, 2, dh, G53, 0.5).capture()
+    for _ in range(9):  # two eager steps ran during capture; 9 replays of 2 steps
+        graph.step(2)
+        torch.cuda.synchronize()
+    close(eager.current.cpu().numpy(), ora, 1e-12, "smooth 20 steps")
+    assert torch.equal(eager.current, graph.current)
+    assert eager.time() == graph.time() == pytest.approx(t_ora, rel=1e-13)
+
+
+# ------------------------------------------------------------------ CFL, sums, stats
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_cfl_and_sums(gpu, dtype):
+    st, dh = W.cosmo_like(n=32)
+    st = st.to(dtype)
+    host = st.double().numpy()
+    dt_g = hydro.cfl_dt(st.to(gpu), dh, G53, 0.5)
+    dt_o = oracle.cfl_dt(host, dh, G53, 0.5)
+    assert dt_g == pytest.approx(dt_o, rel=1e-15)
+    s_g = np.array(hydro.conserved_sums(st.to(gpu), dh))
+    s_o = oracle.conserved_sums(host, dh)
+    scale = dh ** 3 * np.abs(host).reshape(host.shape[0], 5, -1).sum(axis=(0, 2))
+    assert np.all(np.abs(s_g - s_o) <= 1e-14 * scale)
+
+
+def test_solver_stats_equal_group_stats(gpu):
+    """The solver's fused epilogue and the stand-alone stats kernel agree bitwise
+    on the sums and the signal speed of the same output."""
+    st, dh = W.smooth_modes(n=32)
+    gp = hydro.pack_periodic(st.to(gpu), 2, 2, 2)
+    dt_dev = torch.tensor([1e-3], dtype=torch.float64, device=gpu)
+    dh_dev = torch.tensor([dh], dtype=torch.float64, device=gpu)
+    s1 = torch.empty((8, 8), dtype=torch.float64, device=gpu)
+    out = hydro.hydro_solve_batched(gp, None, dt_dev, dh_dev, G53, group_stats=s1)
+    s2 = hydro.group_stats(out, G53)
+    assert torch.equal(s1[:, :6], s2[:, :6])
+
+
+def test_determinism(gpu):
+    st, dh = W.cosmo_like(n=32)
+    gp = hydro.pack_periodic(st.to(gpu), 2, 2, 2)
+    a = hydro.hydro_solve(gp, 1e-4, dh, G53)
+    b = hydro.hydro_solve(gp, 1e-4, dh, G53)
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------ batched levels
+
+def test_batched_levels_fp64(gpu):
+    """Groups of three levels with their own dt and dh in one launch: each group
+    matches the oracle run with that group's dt and dh."""
+    r = np.random.default_rng(12)
+    st, dh0 = W.smooth_modes(n=32)
+    P = oracle.pack_periodic(st.numpy(), 2, 2, 2)
+    lev = r.integers(0, 3, size=P.shape[0]).astype(np.int8)
+    dts = np.array([2e-3, 1e-3, 5e-4])
+    dhs = np.array([dh0, dh0 / 2, dh0 / 4])
+    out = hydro.hydro_solve_batched(torch.from_numpy(P).to(gpu), torch.from_numpy(lev).to(gpu),
+                                    torch.from_numpy(dts).to(gpu), torch.from_numpy(dhs).to(gpu), G53)
+    o = out.cpu().numpy()
+    for L in range(3):
+        sel = lev == L
+        if sel.any():
+            ora, _, _ = oracle.hydro_solve(P[sel], dts[L], dhs[L], G53)
+            close(o[sel], ora, 1e-12, f"level {L}")
+
+
+def test_step_reduce_per_level(gpu):
+    st, dh = W.cosmo_like(n=32)
+    gpu_st = st.to(gpu)
+    stats = hydro.group_stats(gpu_st, G53)
+    lev = torch.tensor([0, 1, 0, 2, 1, 0, 2, 2], dtype=torch.int8)
+    dhs = torch.tensor([1.0, 0.5, 0.25], dtype=torch.float64)
+    dt, tot = hydro.step_reduce(stats, lev.to(gpu), dhs.to(gpu), 0.5)
+    host = st.numpy()
+    for L in range(3):
+        sel = (lev == L).numpy()
+        want = oracle.cfl_dt(host[sel], float(dhs[L]), G53, 0.5)
+        assert float(dt[L]) == pytest.approx(want, rel=1e-15)
+    want = sum(oracle.conserved_sums(host[(lev == L).numpy()], float(dhs[L])) for L in range(3))
+    np.testing.assert_allclose(tot[:5].cpu().numpy(), want, rtol=1e-13)
+
+
+# ------------------------------------------------------------------ full size
+
+def test_workload2_full_size_fp64_and_fp32(gpu):
+    """256^3 smooth flow (4096 groups), the benchmark's input, one step: every
+    group against the oracle in FP64, and FP32 within 1e-5."""
+    st, dh = W.smooth_modes(n=256, device=gpu)
+    dt = 0.5 * dh / 3.0  # fixed, well inside the CFL limit of this flow
+    gp = hydro.pack_periodic(st, 16, 16, 16)
+    out = hydro.hydro_solve(gp, dt, dh, G53).cpu().numpy()
+    out32 = hydro.hydro_solve(hydro.pack_periodic(st.float(), 16, 16, 16), dt, dh, G53).cpu().double().numpy()
+    host = st.cpu().numpy()
+    del gp
+    ora, _, cnt = oracle.hydro_solve(oracle.pack_periodic(host, 16, 16, 16), dt, dh, G53)
+    assert cnt == (0, 0)
+    close(out, ora, 1e-12, "workload 2 fp64")
+    ora32, _, _ = oracle.hydro_solve(oracle.pack_periodic(st.float().double().cpu().numpy(), 16, 16, 16),
+                                     dt, dh, G53)
+    close(out32, ora32, 1e-5, "workload 2 fp32")
