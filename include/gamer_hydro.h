@@ -27,7 +27,8 @@
  *                      for x, (k,i) for y, (j,i) for z.
  *      group stats     [n][8] doubles: sum rho, sum m_x, sum m_y, sum m_z,
  *                      sum E over the 16^3 output cells (not multiplied by
- *                      dh^3), max over output cells of |u|+|v|+|w|+3 c_s,
+ *                      dh^3), max over output cells of |u|+|v|+|w|+3 c_s
+ *                      (evaluated in the working precision),
  *                      number of cells whose half-step prediction fell back
  *                      to first order, number of faces whose Roe flux fell
  *                      back to HLLE.
@@ -135,7 +136,8 @@ int gamer_group_stats_f32(const float *groups, int64_t n_groups, double gamma,
 
 /* ---- CFL time step ------------------------------------------------------
  * dt = cfl * dh / max over all interior cells of (|u| + |v| + |w| + 3 c_s), the
- * 3D unsplit stability bound (the paper does not state its CFL form).
+ * 3D unsplit stability bound (the paper does not state its CFL form),
+ * evaluated in the working precision (the _f32 variant in float).
  * groups: interior [n][5][16][16][16].  dt_out is a device pointer when
  * dt_out_is_device != 0 (asynchronous), else a host pointer (the call then
  * synchronises the stream).  Uses library scratch of 64 B per group. */

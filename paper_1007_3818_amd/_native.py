@@ -7,7 +7,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgamer_hydro.so")
+# GAMER_HYDRO_LIB selects another build of the same library (tuning variants)
+LIB_PATH = os.environ.get("GAMER_HYDRO_LIB") or os.path.join(HERE, "libgamer_hydro.so")
 
 GAMER_OK = 0
 GAMER_EINVAL = -1

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgamer_hydro.so")
 SOURCES = ["solver.hip", "aux_kernels.hip", "abi.hip"]
-HEADERS = ["internal.h"]
+HEADERS = ["internal.h", "device_math.h"]
 ARCH = "gfx950"
 
 FLAGS = [
@@ -24,29 +24,46 @@ FLAGS = [
 ]
 
 
+# hipcc's host pass does not know the GPU target feature above and says so once
+# per compile; that line is dropped, everything else is shown
+_HARMLESS = "'-packed-fp32-ops' is not a recognized feature for this target"
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    msg = "\n".join(l for l in r.stdout.splitlines() if _HARMLESS not in l)
+    if msg.strip():
+        print(msg, flush=True)
+    if r.returncode != 0:
+        raise subprocess.CalledProcessError(r.returncode, cmd)
+
+
 def sources():
     return [os.path.join(CSRC, s) for s in SOURCES]
 
 
-def build(verbose: bool = False, extra=None) -> str:
+def build(verbose: bool = False, extra=None, out=None, bdir=None) -> str:
+    """Compile every source and link the library (to `out`, default in-tree).
+    `extra` adds compiler flags, e.g. -D tunables of a tuning variant."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
-    bdir = os.path.join(HERE, "_build")
+    bdir = bdir or os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in sources():
         obj = os.path.join(bdir, os.path.basename(src) + ".o")
         cmd = [hipcc, *FLAGS, *(extra or []), "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        _run(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    target = out or LIB
+    tmp = target + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    _run(cmd)
+    os.replace(tmp, target)
+    return target
 
 
 if __name__ == "__main__":

@@ -1,5 +1,6 @@
 // aux_kernels.hip -- periodic ghost fill, per-group stats and the fixed-order
 // reduction of group stats to per-level time steps and conserved totals.
+#include "device_math.h"
 #include "internal.h"
 
 namespace gamer {
@@ -29,15 +30,6 @@ __global__ __launch_bounds__(256) void pack_periodic_kernel(const T *__restrict_
     }
 }
 
-__device__ __forceinline__ double signal_speed(double r, double mx, double my, double mz,
-                                               double e, double g) {
-#pragma clang fp contract(off)
-    const double u = mx / r, v = my / r, w = mz / r;
-    const double p = (g - 1.0) * (e - 0.5 * r * (u * u + v * v + w * w));
-    const double cs = sqrt(g * p / r);
-    return fabs(u) + fabs(v) + fabs(w) + 3.0 * cs;
-}
-
 // ---- per-group stats of interior groups -----------------------------------
 // 256 threads per group, thread (i, j) walks its z column in order; the block
 // reduction matches the solver epilogue's order, so stats of the same cells
@@ -47,17 +39,18 @@ __global__ __launch_bounds__(256) void group_stats_kernel(const T *__restrict__ 
                                                           double gamma, double *__restrict__ stats) {
     __shared__ double red[320 * NSTAT];
     const int t = threadIdx.x;
+    const Consts<T> c = make_consts<T>(gamma, 1.5);
     for (int64_t g = blockIdx.x; g < n; g += gridDim.x) {
         const T *src = groups + g * GOUT + t;
         double st[NSTAT] = {0, 0, 0, 0, 0, 0, 0, 0};
         for (int k = 0; k < NI; ++k) {
-            double u[NV];
+            T u[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                u[v] = double(src[v * NI * NI * NI + k * NI * NI]);
-                st[v] += u[v];
+                u[v] = src[v * NI * NI * NI + k * NI * NI];
+                st[v] += double(u[v]);
             }
-            st[5] = fmax(st[5], signal_speed(u[0], u[1], u[2], u[3], u[4], gamma));
+            st[5] = fmax(st[5], double(signal_speed(u[0], u[1], u[2], u[3], u[4], c)));
         }
         // same layout and order as the solver's 320-thread reduction, with
         // the 64 entries of its ghost-cell threads equal to zero

@@ -24,6 +24,7 @@
 //  - The next padded plane is prefetched into registers one step ahead.
 //  - Per-group stats of the updated cells (sums, max signal speed, fallback
 //    counts) are reduced in a fixed order in the epilogue.
+#include "device_math.h"
 #include "internal.h"
 
 namespace gamer {
@@ -37,11 +38,7 @@ struct alignas(16) Lds {
     T w[3][NV][NPL];       // primitive planes, ring indexed by (plane + 3) % 3
     T sx[NV][NI][NI + 1];  // [v][j][f]: +x state of cell f-1, then x flux at face f
     T sy[NV][NI + 1][NI];  // [v][f][i]: +y state of cell f-1, then y flux at face f
-};
-
-template <typename T>
-struct Consts {
-    T g, gm1, igm1, theta, half;
+    double dxy[NV][NINNER];  // (dF_x + dF_y) of each interior cell of the previous plane
 };
 
 template <typename T>
@@ -53,7 +50,7 @@ __device__ __forceinline__ T limiter(T a, T b, T theta) {
 }
 
 // Physical flux along direction D of primitive state (rho, u_x, u_y, u_z, p);
-// accumulates s += sign * F.
+// writes F.
 template <int D, typename T>
 __device__ __forceinline__ void flux_prim(const T w[NV], const Consts<T> &c, T f[NV]) {
     const T un = w[1 + D];
@@ -82,9 +79,24 @@ __device__ __forceinline__ bool physical(const T u[NV]) {
     return u[0] > T(0) && T(2) * u[0] * u[4] > u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
 }
 
+// Physical flux of a rotated conserved state (normal = component 1), given
+// its normal velocity and pressure.
 template <typename T>
-__device__ __forceinline__ void hlle(const T L[NV], const T R[NV], const T FL[NV], const T FR[NV],
-                                     T SL, T SR, T F[NV]) {
+__device__ __forceinline__ void rot_flux(const T U[NV], T un, T p, T F[NV]) {
+    F[0] = U[1];
+    F[1] = U[1] * un + p;
+    F[2] = U[2] * un;
+    F[3] = U[3] * un;
+    F[4] = (U[4] + p) * un;
+}
+
+// HLLE flux (Einfeldt) with signal speeds SL, SR.
+template <typename T>
+__device__ __forceinline__ void hlle(const T L[NV], const T R[NV], T uL, T pL, T uR, T pR, T SL, T SR,
+                                  T F[NV]) {
+    T FL[NV], FR[NV];
+    rot_flux(L, uL, pL, FL);
+    rot_flux(R, uR, pR, FR);
     if (SL >= T(0)) {
 #pragma unroll
         for (int m = 0; m < NV; ++m) F[m] = FL[m];
@@ -92,7 +104,7 @@ __device__ __forceinline__ void hlle(const T L[NV], const T R[NV], const T FL[NV
 #pragma unroll
         for (int m = 0; m < NV; ++m) F[m] = FR[m];
     } else {
-        const T id = T(1) / (SR - SL);
+        const T id = rcp(SR - SL);
 #pragma unroll
         for (int m = 0; m < NV; ++m) F[m] = (SR * FL[m] - SL * FR[m] + SL * SR * (R[m] - L[m])) * id;
     }
@@ -101,38 +113,42 @@ __device__ __forceinline__ void hlle(const T L[NV], const T R[NV], const T FL[NV
 // Roe flux between rotated conserved states (component 1 = normal momentum).
 // Harten-Hyman entropy fix on the acoustic waves, HLLE when a2 <= 0 or an
 // intermediate state is unphysical.  Returns true when HLLE was used.
+// Arithmetic layout: one reciprocal square root per side gives sqrt(rho) and
+// 1/rho; one of a2 gives a and 1/a; the intermediate states' positivity and
+// rho c come from Q = 2 rho E - |m|^2 (p > 0 <=> Q > 0, (rho c)^2 = gq Q), so
+// they need no reciprocal unless the entropy fix is active on that lane.
 template <typename T>
 __device__ __forceinline__ bool roe(const T L[NV], const T R[NV], const Consts<T> &c, T F[NV]) {
     const T h = c.half;
-    const T irL = T(1) / L[0], irR = T(1) / R[0];
+    const T qL = rsq(L[0]), qR = rsq(R[0]);
+    const T irL = qL * qL, irR = qR * qR;
     const T uL = L[1] * irL, vL = L[2] * irL, wL = L[3] * irL;
     const T uR = R[1] * irR, vR = R[2] * irR, wR = R[3] * irR;
-    const T pL = c.gm1 * (L[4] - h * L[0] * (uL * uL + vL * vL + wL * wL));
-    const T pR = c.gm1 * (R[4] - h * R[0] * (uR * uR + vR * vR + wR * wR));
-    const T FL[NV] = {L[1], L[1] * uL + pL, L[2] * uL, L[3] * uL, (L[4] + pL) * uL};
-    const T FR[NV] = {R[1], R[1] * uR + pR, R[2] * uR, R[3] * uR, (R[4] + pR) * uR};
-    const T cL = sqrt(c.g * pL * irL), cR = sqrt(c.g * pR * irR);
+    const T pL = c.gm1 * (L[4] - h * (L[1] * uL + L[2] * vL + L[3] * wL));
+    const T pR = c.gm1 * (R[4] - h * (R[1] * uR + R[2] * vR + R[3] * wR));
+    const T cL = sqrt_(c.g * pL * irL), cR = sqrt_(c.g * pR * irR);
 
-    const T sL = sqrt(L[0]), sR = sqrt(R[0]);
-    const T is = T(1) / (sL + sR);
-    const T u = (sL * uL + sR * uR) * is;
-    const T v = (sL * vL + sR * vR) * is;
-    const T w = (sL * wL + sR * wR) * is;
-    const T H = (sL * ((L[4] + pL) * irL) + sR * ((R[4] + pR) * irR)) * is;
+    // Roe averages with weights sqrt(rho): sqrt(rho) u = m / sqrt(rho)
+    const T is = rcp(L[0] * qL + R[0] * qR);
+    const T u = (L[1] * qL + R[1] * qR) * is;
+    const T v = (L[2] * qL + R[2] * qR) * is;
+    const T w = (L[3] * qL + R[3] * qR) * is;
+    const T H = ((L[4] + pL) * qL + (R[4] + pR) * qR) * is;
     const T q2 = u * u + v * v + w * w;
     const T a2 = c.gm1 * (H - h * q2);
     if (!(a2 > T(0))) {
-        hlle(L, R, FL, FR, uL - cL, uR + cR, F);
+        hlle(L, R, uL, pL, uR, pR, uL - cL, uR + cR, F);
         return true;
     }
-    const T a = sqrt(a2);
+    const T ia = rsq(a2);
+    const T a = a2 * ia;
     const T D0 = R[0] - L[0], D1 = R[1] - L[1], D2 = R[2] - L[2], D3 = R[3] - L[3],
             D4 = R[4] - L[4];
     const T al3 = D2 - v * D0;
     const T al4 = D3 - w * D0;
     const T d5 = D4 - al3 * v - al4 * w;
-    const T al2 = c.gm1 / a2 * (D0 * (H - u * u) + u * D1 - d5);
-    const T al1 = (D0 * (u + a) - D1 - a * al2) / (T(2) * a);
+    const T al2 = c.gm1 * (ia * ia) * (D0 * (H - u * u) + u * D1 - d5);
+    const T al1 = (D0 * (u + a) - D1 - a * al2) * (h * ia);
     const T al5 = D0 - (al1 + al2);
     const T ua = u * a;
 
@@ -141,32 +157,40 @@ __device__ __forceinline__ bool roe(const T L[NV], const T R[NV], const Consts<T
                       L[4] + al1 * (H - ua)};
     const T Rs[NV] = {R[0] - al5, R[1] - al5 * (u + a), R[2] - al5 * v, R[3] - al5 * w,
                       R[4] - al5 * (H + ua)};
-    if (!physical(Ls) || !physical(Rs)) {
-        hlle(L, R, FL, FR, fmin(uL - cL, u - a), fmax(uR + cR, u + a), F);
+    const T QL = T(2) * Ls[0] * Ls[4] - (Ls[1] * Ls[1] + Ls[2] * Ls[2] + Ls[3] * Ls[3]);
+    const T QR = T(2) * Rs[0] * Rs[4] - (Rs[1] * Rs[1] + Rs[2] * Rs[2] + Rs[3] * Rs[3]);
+    if (!(Ls[0] > T(0) && QL > T(0) && Rs[0] > T(0) && QR > T(0))) {
+        hlle(L, R, uL, pL, uR, pR, fmin(uL - cL, u - a), fmax(uR + cR, u + a), F);
         return true;
     }
-    const T irLs = T(1) / Ls[0], irRs = T(1) / Rs[0];
-    const T uLs = Ls[1] * irLs, uRs = Rs[1] * irRs;
-    const T vLs = Ls[2] * irLs, vRs = Rs[2] * irRs;
-    const T wLs = Ls[3] * irLs, wRs = Rs[3] * irRs;
-    const T pLs = c.gm1 * (Ls[4] - h * Ls[0] * (uLs * uLs + vLs * vLs + wLs * wLs));
-    const T pRs = c.gm1 * (Rs[4] - h * Rs[0] * (uRs * uRs + vRs * vRs + wRs * wRs));
-    const T cLs = sqrt(c.g * pLs * irLs), cRs = sqrt(c.g * pRs * irRs);
+    const T rcLs = sqrt_(c.gq * QL), rcRs = sqrt_(c.gq * QR);  // rho* c*
 
+    // Harten-Hyman: wave 1 between L (speed uL - cL) and L* (speed (m* - rho* c*)/rho*),
+    // wave 5 between R* (speed (m* + rho* c*)/rho*) and R (speed uR + cR).  The fix is
+    // active when |lambda| < lambda - lambda_left or |lambda| < lambda_right - lambda.
     const T lam1 = u - a, lam5 = u + a;
-    const T e1 = fmax(T(0), fmax(lam1 - (uL - cL), (uLs - cLs) - lam1));
-    const T e5 = fmax(T(0), fmax(lam5 - (uRs + cRs), (uR + cR) - lam5));
-    const T ab1 = fabs(lam1) < e1 ? (lam1 * lam1 + e1 * e1) / (T(2) * e1) : fabs(lam1);
-    const T ab5 = fabs(lam5) < e5 ? (lam5 * lam5 + e5 * e5) / (T(2) * e5) : fabs(lam5);
+    const T t1a = lam1 - (uL - cL);
+    const T t1b_r = (Ls[1] - rcLs) - lam1 * Ls[0];  // (lambda_right - lambda) rho*
+    const T t5b = (uR + cR) - lam5;
+    const T t5a_r = lam5 * Rs[0] - (Rs[1] + rcRs);  // (lambda - lambda_left) rho*
+    T ab1 = fabs(lam1), ab5 = fabs(lam5);
+    if (ab1 < t1a || ab1 * Ls[0] < t1b_r) {
+        const T e = fmax(t1a, t1b_r * rcp(Ls[0]));
+        ab1 = (lam1 * lam1 + e * e) * (h * rcp(e));
+    }
+    if (ab5 < t5b || ab5 * Rs[0] < t5a_r) {
+        const T e = fmax(t5b, t5a_r * rcp(Rs[0]));
+        ab5 = (lam5 * lam5 + e * e) * (h * rcp(e));
+    }
     const T ab2 = fabs(u);
 
     const T c1 = al1 * ab1, c2 = al2 * ab2, c3 = al3 * ab2, c4 = al4 * ab2, c5 = al5 * ab5;
-    F[0] = h * (FL[0] + FR[0]) - h * ((c1 + c2) + c5);
-    F[1] = h * (FL[1] + FR[1]) - h * ((c1 * (u - a) + c2 * u) + c5 * (u + a));
-    F[2] = h * (FL[2] + FR[2]) - h * (((c1 * v + c2 * v) + c3) + c5 * v);
-    F[3] = h * (FL[3] + FR[3]) - h * (((c1 * w + c2 * w) + c4) + c5 * w);
-    F[4] = h * (FL[4] + FR[4]) -
-           h * ((((c1 * (H - ua) + c2 * (h * q2)) + c3 * v) + c4 * w) + c5 * (H + ua));
+    F[0] = h * ((L[1] + R[1]) - ((c1 + c2) + c5));
+    F[1] = h * ((L[1] * uL + pL + R[1] * uR + pR) - ((c1 * (u - a) + c2 * u) + c5 * (u + a)));
+    F[2] = h * ((L[2] * uL + R[2] * uR) - (((c1 * v + c2 * v) + c3) + c5 * v));
+    F[3] = h * ((L[3] * uL + R[3] * uR) - (((c1 * w + c2 * w) + c4) + c5 * w));
+    F[4] = h * (((L[4] + pL) * uL + (R[4] + pR) * uR) -
+                ((((c1 * (H - ua) + c2 * (h * q2)) + c3 * v) + c4 * w) + c5 * (H + ua)));
     return false;
 }
 
@@ -185,17 +209,6 @@ __device__ __forceinline__ bool roe_dir(const T UL[NV], const T UR[NV], const Co
     F[t2] = Fr[3];
     F[4] = Fr[4];
     return fb;
-}
-
-// |u| + |v| + |w| + 3 c_s of a conserved state, without contraction so that the
-// value is the plain IEEE evaluation of the formula.
-__device__ __forceinline__ double signal_speed(double r, double mx, double my, double mz,
-                                               double e, double g) {
-#pragma clang fp contract(off)
-    const double u = mx / r, v = my / r, w = mz / r;
-    const double p = (g - 1.0) * (e - 0.5 * r * (u * u + v * v + w * w));
-    const double cs = sqrt(g * p / r);
-    return fabs(u) + fabs(v) + fabs(w) + 3.0 * cs;
 }
 
 // Fixed-order reduction of NSTAT doubles per thread over NTHREADS threads:
@@ -234,8 +247,28 @@ __device__ __forceinline__ void block_reduce_stats(double st[NSTAT], double *red
     __syncthreads();
 }
 
+// Waves per SIMD the register allocation must allow (build-time tunables).
+// LDS allows three 5-wave float work-groups per CU (45 KB each) and two double
+// ones (80 KB each).
+#ifndef GAMER_F32_WAVES_PER_SIMD
+#define GAMER_F32_WAVES_PER_SIMD 4
+#endif
+#ifndef GAMER_F64_WAVES_PER_SIMD
+#define GAMER_F64_WAVES_PER_SIMD 2
+#endif
 template <typename T>
-__global__ __launch_bounds__(NTHR) void solve_kernel(SolveParams<T> P) {
+struct Occupancy;
+template <>
+struct Occupancy<float> {
+    static constexpr int waves_per_simd = GAMER_F32_WAVES_PER_SIMD;
+};
+template <>
+struct Occupancy<double> {
+    static constexpr int waves_per_simd = GAMER_F64_WAVES_PER_SIMD;
+};
+
+template <typename T>
+__global__ __launch_bounds__(NTHR, Occupancy<T>::waves_per_simd) void solve_kernel(SolveParams<T> P) {
     __shared__ Lds<T> S;
     const int t = threadIdx.x;
 
@@ -261,7 +294,7 @@ __global__ __launch_bounds__(NTHR) void solve_kernel(SolveParams<T> P) {
     const bool do_x = ci >= 0 && cj >= 0 && cj < NI;          // solves x face ci
     const bool do_y = cj >= 0 && ci >= 0 && ci < NI;          // solves y face cj
 
-    const Consts<T> c{T(P.gamma), T(P.gamma - 1.0), T(1.0 / (P.gamma - 1.0)), T(P.theta), T(0.5)};
+    const Consts<T> c = make_consts<T>(P.gamma, P.theta);
 
     for (int64_t g = blockIdx.x; g < P.n_groups; g += gridDim.x) {
         double dt = P.dt, dh = P.dh;
@@ -289,7 +322,7 @@ __global__ __launch_bounds__(NTHR) void solve_kernel(SolveParams<T> P) {
         auto store = [&](int plane) {  // prefetched conserved -> primitive LDS plane
             const int slot = (plane + 3) % 3;
             {
-                const T ir = T(1) / pre0[0];
+                const T ir = rcp(pre0[0]);
                 const T u = pre0[1] * ir, v = pre0[2] * ir, w = pre0[3] * ir;
                 S.w[slot][0][p0] = pre0[0];
                 S.w[slot][1][p0] = u;
@@ -298,7 +331,7 @@ __global__ __launch_bounds__(NTHR) void solve_kernel(SolveParams<T> P) {
                 S.w[slot][4][p0] = c.gm1 * (pre0[4] - c.half * pre0[0] * (u * u + v * v + w * w));
             }
             if (has1) {
-                const T ir = T(1) / pre1[0];
+                const T ir = rcp(pre1[0]);
                 const T u = pre1[1] * ir, v = pre1[2] * ir, w = pre1[3] * ir;
                 S.w[slot][0][p1] = pre1[0];
                 S.w[slot][1][p1] = u;
@@ -317,15 +350,14 @@ __global__ __launch_bounds__(NTHR) void solve_kernel(SolveParams<T> P) {
         // carried across sweep steps
         T zp[NV];            // +z state of this column at the previous plane
         T fz[NV];            // z flux below the current plane
-        double dxy[NV];      // (dF_x + dF_y) of the previous plane
-        double st[NSTAT];    // group stats
+        double st[6];        // sums of the 5 conserved variables, max signal speed
+        int n_pred = 0, n_roe = 0;  // fallback counts
 #pragma unroll
-        for (int q = 0; q < NSTAT; ++q) st[q] = 0.0;
+        for (int q = 0; q < 6; ++q) st[q] = 0.0;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             zp[v] = T(0);
             fz[v] = T(0);
-            dxy[v] = 0.0;
         }
 
         for (int k = -1; k <= NI; ++k) {
@@ -404,7 +436,7 @@ __global__ __launch_bounds__(NTHR) void solve_kernel(SolveParams<T> P) {
                 face(dW[2], T(1), zpn);
                 if (!ok) {
                     // first-order fallback: every face of the cell takes the cell average
-                    st[6] += 1.0;
+                    ++n_pred;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         const T u0 = in[v * NP * NPL + (k + NG) * NPL + pos];
@@ -426,7 +458,7 @@ __global__ __launch_bounds__(NTHR) void solve_kernel(SolveParams<T> P) {
             // z face between planes k-1 and k (registers only)
             T fzn[NV];
             if (inner && k >= 0) {
-                if (roe_dir<2>(zp, zm, c, fzn)) st[7] += 1.0;
+                n_roe += roe_dir<2>(zp, zm, c, fzn);
                 if (P.flux && (k & 7) == 0) {
                     T *dst = P.flux + g * GFLX + ((2 * 3 + (k >> 3)) * NV) * NINNER + cj * NI + ci;
 #pragma unroll
@@ -440,7 +472,7 @@ __global__ __launch_bounds__(NTHR) void solve_kernel(SolveParams<T> P) {
                     T UL[NV], F[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) UL[v] = S.sx[v][cj][ci];
-                    if (roe_dir<0>(UL, xm, c, F)) st[7] += 1.0;
+                    n_roe += roe_dir<0>(UL, xm, c, F);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) S.sx[v][cj][ci] = F[v];
                     if (P.flux && (ci & 7) == 0) {
@@ -453,7 +485,7 @@ __global__ __launch_bounds__(NTHR) void solve_kernel(SolveParams<T> P) {
                     T UL[NV], F[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) UL[v] = S.sy[v][cj][ci];
-                    if (roe_dir<1>(UL, ym, c, F)) st[7] += 1.0;
+                    n_roe += roe_dir<1>(UL, ym, c, F);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) S.sy[v][cj][ci] = F[v];
                     if (P.flux && (cj & 7) == 0) {
@@ -471,23 +503,23 @@ __global__ __launch_bounds__(NTHR) void solve_kernel(SolveParams<T> P) {
                     const int kk = k - 1;
                     T *dst = P.out + g * GOUT + kk * NINNER + cj * NI + ci;
                     const T *src = in + (kk + NG) * NPL + pos;
-                    double un[NV];
+                    T un[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         const double dfz = double(fzn[v]) - double(fz[v]);
-                        const double r = double(src[v * NP * NPL]) - dtdh * (dxy[v] + dfz);
+                        const double r = double(src[v * NP * NPL]) - dtdh * (S.dxy[v][t] + dfz);
                         const T o = T(r);
                         dst[v * NI * NINNER] = o;
-                        un[v] = double(o);
-                        st[v] += un[v];
+                        un[v] = o;
+                        st[v] += double(o);
                     }
-                    st[5] = fmax(st[5], signal_speed(un[0], un[1], un[2], un[3], un[4], P.gamma));
+                    st[5] = fmax(st[5], double(signal_speed(un[0], un[1], un[2], un[3], un[4], c)));
                 }
                 if (!edge) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
-                        dxy[v] = (double(S.sx[v][cj][ci + 1]) - double(S.sx[v][cj][ci])) +
-                                 (double(S.sy[v][cj + 1][ci]) - double(S.sy[v][cj][ci]));
+                        S.dxy[v][t] = (double(S.sx[v][cj][ci + 1]) - double(S.sx[v][cj][ci])) +
+                                      (double(S.sy[v][cj + 1][ci]) - double(S.sy[v][cj][ci]));
                 }
                 if (k >= 0) {
 #pragma unroll
@@ -499,8 +531,10 @@ __global__ __launch_bounds__(NTHR) void solve_kernel(SolveParams<T> P) {
         }
 
         if (P.stats) {
+            double all[NSTAT] = {st[0], st[1], st[2], st[3], st[4], st[5], double(n_pred),
+                                 double(n_roe)};
             // S.w is free now (B3 of the last step passed); reuse it for the reduction
-            block_reduce_stats<NTHR>(st, reinterpret_cast<double *>(&S.w[0][0][0]),
+            block_reduce_stats<NTHR>(all, reinterpret_cast<double *>(&S.w[0][0][0]),
                                      P.stats + g * NSTAT);
         } else {
             __syncthreads();

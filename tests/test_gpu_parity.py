@@ -183,7 +183,9 @@ def test_cfl_and_sums(gpu, dtype):
     host = st.double().numpy()
     dt_g = hydro.cfl_dt(st.to(gpu), dh, G53, 0.5)
     dt_o = oracle.cfl_dt(host, dh, G53, 0.5)
-    assert dt_g == pytest.approx(dt_o, rel=1e-15)
+    # the signal speed is evaluated in the working precision with refined
+    # (FP64) or hardware (FP32) reciprocal and square root
+    assert dt_g == pytest.approx(dt_o, rel=4e-15 if dtype == torch.float64 else 1e-6)
     s_g = np.array(hydro.conserved_sums(st.to(gpu), dh))
     s_o = oracle.conserved_sums(host, dh)
     scale = dh ** 3 * np.abs(host).reshape(host.shape[0], 5, -1).sum(axis=(0, 2))
@@ -243,7 +245,7 @@ def test_step_reduce_per_level(gpu):
     for L in range(3):
         sel = (lev == L).numpy()
         want = oracle.cfl_dt(host[sel], float(dhs[L]), G53, 0.5)
-        assert float(dt[L]) == pytest.approx(want, rel=1e-15)
+        assert float(dt[L]) == pytest.approx(want, rel=4e-15)
     want = sum(oracle.conserved_sums(host[(lev == L).numpy()], float(dhs[L])) for L in range(3))
     np.testing.assert_allclose(tot[:5].cpu().numpy(), want, rtol=1e-13)
 
