@@ -62,12 +62,25 @@ extern "C" {
 
 #define GAMER_MAX_LEVELS 32 /* largest n_levels of the batched entry points */
 
-/* Tunables of the reading of the method.  NULL selects the defaults. */
+/* Tunables.  NULL, or a zero-initialised struct, selects the defaults. */
 typedef struct gamer_opts {
     /* Generalised-minmod parameter of the slope limiter, 1 <= theta <= 2
-     * (1: minmod, 2: monotonised central).  Default 1.5. */
+     * (1: minmod, 2: monotonised central); 0 selects the default 1.5. */
     double theta;
+    /* Compiled solver variant, 0 .. gamer_solver_variants(f32)-1 (0 is the
+     * default).  Variants differ only in the register budget they were built
+     * for (waves per SIMD); their results are bitwise identical. */
+    int32_t variant;
+    /* Work-groups launched: 0 launches one per group; g > 0 launches
+     * min(g, n_groups) persistent work-groups that stride over the groups. */
+    int32_t grid;
 } gamer_opts;
+
+/* Number of compiled solver variants for the float (f32 != 0) or double path,
+ * and the waves per SIMD variant v was built for (0 for an unknown v).  Used by
+ * the tuner that picks a variant and a grid for a given batch. */
+int gamer_solver_variants(int f32);
+int gamer_solver_variant_waves(int f32, int variant);
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int gamer_version(void);
@@ -161,7 +174,8 @@ int gamer_conserved_sums_f32(const float *groups, int64_t n_groups, double dh,
  * padded: [gx*gy*gz][5][20][20][20]; each padded cell takes the value of
  * the cell at its periodically wrapped global position.  The paper prepares
  * ghost zones on the host from the AMR hierarchy; this covers the uniform
- * periodic case on the device.  Errors: GAMER_EINVAL for gx, gy, gz < 1. */
+ * periodic case on the device.  Errors: GAMER_EINVAL for gx, gy, gz < 1 or
+ * gx*gy*gz*100 > INT32_MAX (about 21 million groups). */
 int gamer_pack_periodic(const double *state, int gx, int gy, int gz, double *padded);
 int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *padded);
 

@@ -23,7 +23,7 @@ _I64 = ctypes.c_int64
 
 
 class GamerOpts(ctypes.Structure):
-    _fields_ = [("theta", ctypes.c_double)]
+    _fields_ = [("theta", ctypes.c_double), ("variant", ctypes.c_int32), ("grid", ctypes.c_int32)]
 
 
 _PO = ctypes.POINTER(GamerOpts)
@@ -34,6 +34,8 @@ SIGNATURES = {
     "gamer_set_stream": (_I, [_P]),
     "gamer_get_stream": (_P, []),
     "gamer_last_error": (ctypes.c_char_p, []),
+    "gamer_solver_variants": (_I, [_I]),
+    "gamer_solver_variant_waves": (_I, [_I, _I]),
     "gamer_hydro_solve": (_I, [_P, _I64, _D, _D, _D, _P, _P]),
     "gamer_hydro_solve_f32": (_I, [_P, _I64, _D, _D, _D, _P, _P]),
     "gamer_hydro_solve_batched": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO]),

@@ -1,0 +1,91 @@
+"""Launch-shape tuner for the batched solver.
+
+For a given batch (precision, group count) it times every compiled solver
+variant (register budget / waves per SIMD) with one work-group per group and
+with persistent grids of 1-4 work-groups per CU, checks that all candidates
+produce bitwise-identical output, and returns (and caches) the fastest.
+
+The cache is a JSON file keyed by device name, precision and the group count
+rounded up to a power of two; ``GAMER_TUNE_CACHE`` overrides its path.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import hydro
+
+
+def cache_path() -> str:
+    return os.environ.get("GAMER_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "gamer_hydro", "tune.json")
+
+
+def _key(dtype, n_groups: int) -> str:
+    name = torch.cuda.get_device_name(0)
+    bucket = 1 << max(0, (int(n_groups) - 1).bit_length())
+    return f"{name}|{'f32' if dtype == torch.float32 else 'f64'}|{bucket}"
+
+
+def candidates(dtype, n_groups: int):
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    grids = [0] + [n_cu * k for k in (1, 2, 3, 4) if n_cu * k < n_groups]
+    return [(v, g) for v in range(len(hydro.solver_variants(dtype))) for g in grids]
+
+
+def _load():
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(table):
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # an unwritable cache only costs re-tuning
+
+
+def tune(padded: torch.Tensor, dt_dev: torch.Tensor, dh_dev: torch.Tensor, gamma: float,
+         level=None, reps: int = 5, use_cache: bool = True) -> dict:
+    """Return {"variant", "grid", "ms", "table"} for this batch."""
+    key = _key(padded.dtype, padded.shape[0])
+    if use_cache:
+        hit = _load().get(key)
+        if hit is not None:
+            return dict(hit, cached=True)
+    n = padded.shape[0]
+    out = torch.empty((n, 5, 16, 16, 16), dtype=padded.dtype, device=padded.device)
+    ref = None
+    table = []
+    for v, g in candidates(padded.dtype, n):
+        hydro.hydro_solve_batched(padded, level, dt_dev, dh_dev, gamma, out=out, variant=v, grid=g)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = out.clone()
+        elif not torch.equal(out, ref):
+            raise RuntimeError(f"solver variant {v} grid {g} differs from variant 0: refusing to tune")
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            hydro.hydro_solve_batched(padded, level, dt_dev, dh_dev, gamma, out=out, variant=v, grid=g)
+        ev[1].record()
+        torch.cuda.synchronize()
+        table.append({"variant": v, "waves_per_simd": hydro.solver_variants(padded.dtype)[v],
+                      "grid": g, "ms": ev[0].elapsed_time(ev[1]) / reps})
+    best = min(table, key=lambda r: r["ms"])
+    result = {"variant": best["variant"], "grid": best["grid"], "ms": best["ms"], "table": table}
+    if use_cache:
+        t = _load()
+        t[key] = result
+        _save(t)
+    return dict(result, cached=False)

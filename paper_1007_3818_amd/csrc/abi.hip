@@ -71,8 +71,13 @@ int solve_common(const T *in, int64_t n, const int8_t *level, const double *dt_d
     g_err[0] = 0;
     if (n < 0) return fail(GAMER_EINVAL, "n_groups < 0");
     if (!(isfinite(gamma) && gamma > 1.0)) return fail(GAMER_EINVAL, "gamma must be > 1");
-    const double theta = opts ? opts->theta : 1.5;
+    const double theta = (opts && opts->theta != 0.0) ? opts->theta : 1.5;
     if (!(theta >= 1.0 && theta <= 2.0)) return fail(GAMER_EINVAL, "theta must lie in [1, 2]");
+    const int variant = opts ? opts->variant : 0;
+    const int64_t grid = opts ? opts->grid : 0;
+    if (variant < 0 || variant >= solve_variant_count<T>())
+        return fail(GAMER_EINVAL, "variant must lie in [0, %d)", solve_variant_count<T>());
+    if (grid < 0) return fail(GAMER_EINVAL, "grid must be >= 0");
     if (!dt_dev && (!finite_pos(dt) || !finite_pos(dh)))
         return fail(GAMER_EINVAL, "dt and dh must be finite and positive");
     if (n == 0) return GAMER_OK;
@@ -93,7 +98,7 @@ int solve_common(const T *in, int64_t n, const int8_t *level, const double *dt_d
     p.gamma = gamma;
     p.theta = theta;
     p.n_groups = n;
-    return check_hip(launch_solve<T>(p, g_stream), "solver launch");
+    return check_hip(launch_solve<T>(p, variant, grid, g_stream), "solver launch");
 }
 
 template <typename T>
@@ -158,8 +163,8 @@ template <typename T>
 int pack_common(const T *state, int gx, int gy, int gz, T *padded) {
     g_err[0] = 0;
     if (gx < 1 || gy < 1 || gz < 1) return fail(GAMER_EINVAL, "gx, gy, gz must be >= 1");
-    if (int64_t(gx) * NI > (1 << 28) || int64_t(gy) * NI > (1 << 28) || int64_t(gz) * NI > (1 << 28))
-        return fail(GAMER_EINVAL, "grid too large");
+    if (int64_t(gx) * gy * gz * NV * NP > INT32_MAX)
+        return fail(GAMER_EINVAL, "grid too large (gx*gy*gz*100 must fit in int32)");
     if (!state || !padded) return fail(GAMER_EINVAL, "NULL state or padded");
     return check_hip(launch_pack_periodic<T>(state, gx, gy, gz, padded, g_stream), "pack launch");
 }
@@ -188,6 +193,14 @@ int gamer_set_stream(void *hip_stream) {
 void *gamer_get_stream(void) { return g_stream; }
 
 const char *gamer_last_error(void) { return g_err; }
+
+int gamer_solver_variants(int f32) {
+    return f32 ? solve_variant_count<float>() : solve_variant_count<double>();
+}
+
+int gamer_solver_variant_waves(int f32, int variant) {
+    return f32 ? solve_variant_waves<float>(variant) : solve_variant_waves<double>(variant);
+}
 
 int gamer_hydro_solve(const double *groups_in, int64_t n_groups, double dt, double dh,
                       double gamma, double *fluxes_out, double *groups_out) {

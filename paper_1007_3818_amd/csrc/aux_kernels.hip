@@ -7,26 +7,31 @@ namespace gamer {
 namespace {
 
 // ---- same-level periodic ghost fill --------------------------------------
-// One thread per padded output value; consecutive threads write consecutive x.
+// One work-group per (group, variable, padded z-plane): 400 values, written by
+// consecutive threads along x; 32-bit index arithmetic only.
 template <typename T>
 __global__ __launch_bounds__(256) void pack_periodic_kernel(const T *__restrict__ state, int gx,
                                                             int gy, int gz, T *__restrict__ padded,
-                                                            int64_t total) {
+                                                            int n_planes) {
     const int NX = gx * NI, NY = gy * NI, NZ = gz * NI;
-    for (int64_t o = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; o < total;
-         o += int64_t(gridDim.x) * blockDim.x) {
-        const int ip = int(o % NP);
-        const int jp = int((o / NP) % NP);
-        const int kp = int((o / NPL) % NP);
-        const int v = int((o / (NPL * NP)) % NV);
-        const int64_t g = o / GIN;
-        const int bx = int(g % gx), by = int((g / gx) % gy), bz = int(g / (int64_t(gx) * gy));
-        int X = bx * NI + ip - NG, Y = by * NI + jp - NG, Z = bz * NI + kp - NG;
-        X = X < 0 ? X + NX : (X >= NX ? X - NX : X);
-        Y = Y < 0 ? Y + NY : (Y >= NY ? Y - NY : Y);
+    for (int b = blockIdx.x; b < n_planes; b += gridDim.x) {
+        const int kp = b % NP;
+        const int v = (b / NP) % NV;
+        const int g = b / (NP * NV);
+        const int bx = g % gx, by = (g / gx) % gy, bz = g / (gx * gy);
+        int Z = bz * NI + kp - NG;
         Z = Z < 0 ? Z + NZ : (Z >= NZ ? Z - NZ : Z);
-        const int64_t sg = int64_t(X / NI) + int64_t(gx) * (int64_t(Y / NI) + int64_t(gy) * (Z / NI));
-        padded[o] = state[sg * GOUT + int64_t(v) * NI * NI * NI + ((Z % NI) * NI + (Y % NI)) * NI + (X % NI)];
+        const T *src_z = state + int64_t(gx) * gy * (Z / NI) * GOUT + v * (NI * NI * NI) +
+                         (Z % NI) * (NI * NI);
+        T *dst = padded + int64_t(b) * NPL;
+        for (int p = threadIdx.x; p < NPL; p += blockDim.x) {
+            const int ip = p % NP, jp = p / NP;
+            int X = bx * NI + ip - NG, Y = by * NI + jp - NG;
+            X = X < 0 ? X + NX : (X >= NX ? X - NX : X);
+            Y = Y < 0 ? Y + NY : (Y >= NY ? Y - NY : Y);
+            const int sg = X / NI + gx * (Y / NI);
+            dst[p] = src_z[int64_t(sg) * GOUT + (Y % NI) * NI + (X % NI)];
+        }
     }
 }
 
@@ -146,21 +151,17 @@ __global__ __launch_bounds__(RT) void reduce_kernel(const double *__restrict__ s
     }
 }
 
-unsigned grid_for(int64_t work, int per_block) {
-    int64_t b = (work + per_block - 1) / per_block;
-    const int64_t cap = int64_t(256) * 64;  // ample for 256 CUs with grid-stride loops
-    if (b > cap) b = cap;
-    return unsigned(b < 1 ? 1 : b);
-}
-
 }  // namespace
 
 template <typename T>
 hipError_t launch_pack_periodic(const T *state, int gx, int gy, int gz, T *padded, hipStream_t s) {
-    const int64_t total = int64_t(gx) * gy * gz * GIN;
-    if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(pack_periodic_kernel<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, state,
-                       gx, gy, gz, padded, total);
+    // n_planes = groups * 5 * 20 must fit in int (the ABI caps the group count)
+    const int64_t n_planes = int64_t(gx) * gy * gz * NV * NP;
+    if (n_planes == 0) return hipSuccess;
+    const int64_t cap = int64_t(256) * 1024;
+    const unsigned grid = unsigned(n_planes < cap ? n_planes : cap);
+    hipLaunchKernelGGL(pack_periodic_kernel<T>, dim3(grid), dim3(256), 0, s, state, gx, gy, gz,
+                       padded, int(n_planes));
     return hipGetLastError();
 }
 

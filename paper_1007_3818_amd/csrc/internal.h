@@ -34,8 +34,13 @@ struct SolveParams {
     int64_t n_groups;
 };
 
+// Compiled solver variants (occupancy targets) and the launcher.
 template <typename T>
-hipError_t launch_solve(const SolveParams<T> &p, hipStream_t s);
+int solve_variant_count();
+template <typename T>
+int solve_variant_waves(int variant);
+template <typename T>
+hipError_t launch_solve(const SolveParams<T> &p, int variant, int64_t grid, hipStream_t s);
 
 template <typename T>
 hipError_t launch_pack_periodic(const T *state, int gx, int gy, int gz, T *padded, hipStream_t s);

@@ -247,28 +247,25 @@ __device__ __forceinline__ void block_reduce_stats(double st[NSTAT], double *red
     __syncthreads();
 }
 
-// Waves per SIMD the register allocation must allow (build-time tunables).
-// LDS allows three 5-wave float work-groups per CU (45 KB each) and two double
-// ones (80 KB each).
-#ifndef GAMER_F32_WAVES_PER_SIMD
-#define GAMER_F32_WAVES_PER_SIMD 4
-#endif
-#ifndef GAMER_F64_WAVES_PER_SIMD
-#define GAMER_F64_WAVES_PER_SIMD 2
-#endif
+// Variants: the waves per SIMD that the register allocation must allow.  LDS
+// allows three 5-wave float work-groups per CU (45 KB each) and two double
+// ones (80 KB each); more waves trade registers for spills.  The first entry
+// of each list is the default; the tuner may pick another at run time.
 template <typename T>
-struct Occupancy;
+struct Variants;
 template <>
-struct Occupancy<float> {
-    static constexpr int waves_per_simd = GAMER_F32_WAVES_PER_SIMD;
+struct Variants<float> {
+    static constexpr int count = 2;
+    static constexpr int waves[count] = {4, 3};
 };
 template <>
-struct Occupancy<double> {
-    static constexpr int waves_per_simd = GAMER_F64_WAVES_PER_SIMD;
+struct Variants<double> {
+    static constexpr int count = 2;
+    static constexpr int waves[count] = {2, 3};
 };
 
-template <typename T>
-__global__ __launch_bounds__(NTHR, Occupancy<T>::waves_per_simd) void solve_kernel(SolveParams<T> P) {
+template <typename T, int WAVES>
+__global__ __launch_bounds__(NTHR, WAVES) void solve_kernel(SolveParams<T> P) {
     __shared__ Lds<T> S;
     const int t = threadIdx.x;
 
@@ -548,15 +545,42 @@ static_assert(sizeof(Lds<float>::w) >= NTHR * NSTAT * sizeof(double),
 }  // namespace
 
 template <typename T>
-hipError_t launch_solve(const SolveParams<T> &p, hipStream_t s) {
+int solve_variant_count() {
+    return Variants<T>::count;
+}
+
+template <typename T>
+int solve_variant_waves(int v) {
+    return (v >= 0 && v < Variants<T>::count) ? Variants<T>::waves[v] : 0;
+}
+
+// variant < 0 selects the default; grid <= 0 launches one work-group per group,
+// grid > 0 a persistent grid that strides over the groups.
+template <typename T>
+hipError_t launch_solve(const SolveParams<T> &p, int variant, int64_t grid, hipStream_t s) {
     if (p.n_groups <= 0) return hipSuccess;
     const int64_t max_grid = int64_t(1) << 30;
-    const unsigned grid = unsigned(p.n_groups < max_grid ? p.n_groups : max_grid);
-    hipLaunchKernelGGL(solve_kernel<T>, dim3(grid), dim3(NTHR), 0, s, p);
+    int64_t g = grid > 0 ? (grid < p.n_groups ? grid : p.n_groups) : p.n_groups;
+    if (g > max_grid) g = max_grid;
+    const dim3 blocks = dim3(unsigned(g)), threads = dim3(NTHR);
+    switch (variant < 0 ? 0 : variant) {
+        case 0:
+            hipLaunchKernelGGL((solve_kernel<T, Variants<T>::waves[0]>), blocks, threads, 0, s, p);
+            break;
+        case 1:
+            hipLaunchKernelGGL((solve_kernel<T, Variants<T>::waves[1]>), blocks, threads, 0, s, p);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-template hipError_t launch_solve<float>(const SolveParams<float> &, hipStream_t);
-template hipError_t launch_solve<double>(const SolveParams<double> &, hipStream_t);
+template int solve_variant_count<float>();
+template int solve_variant_count<double>();
+template int solve_variant_waves<float>(int);
+template int solve_variant_waves<double>(int);
+template hipError_t launch_solve<float>(const SolveParams<float> &, int, int64_t, hipStream_t);
+template hipError_t launch_solve<double>(const SolveParams<double> &, int, int64_t, hipStream_t);
 
 }  // namespace gamer

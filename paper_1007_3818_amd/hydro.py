@@ -62,8 +62,10 @@ def hydro_solve(groups_in, dt, dh, gamma, out=None, fluxes_out=None):
 
 
 def hydro_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxes_out=None,
-                        group_stats=None, theta=None):
-    """One persistent launch over groups of uneven level; dt and dh read on the device."""
+                        group_stats=None, theta=None, variant=None, grid=None):
+    """One launch over groups of uneven level; dt and dh read on the device.
+    `variant` / `grid` select a compiled solver variant and a persistent grid
+    (see gamer_opts); None keeps the defaults."""
     f32 = _f32(groups_in.dtype)
     _need(groups_in, (NV, NP, NP, NP), groups_in.dtype, "groups_in")
     n = groups_in.shape[0]
@@ -81,7 +83,9 @@ def hydro_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxe
         if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 1:
             raise ValueError(f"{nm} must be a 1-D GPU float64 tensor")
     n_levels = dt_dev.numel()
-    opts = _native.GamerOpts(theta) if theta is not None else None
+    opts = None
+    if theta is not None or variant is not None or grid is not None:
+        opts = _native.GamerOpts(float(theta or 0.0), int(variant or 0), int(grid or 0))
     _stream()
     fn = (_native.lib().gamer_hydro_solve_batched_f32 if f32
           else _native.lib().gamer_hydro_solve_batched)
@@ -161,3 +165,10 @@ def pack_periodic(state, gx, gy, gz, out=None):
     fn = _native.lib().gamer_pack_periodic_f32 if f32 else _native.lib().gamer_pack_periodic
     _native.check(fn(_ptr(state), int(gx), int(gy), int(gz), _ptr(out)))
     return out
+
+
+def solver_variants(dtype) -> list:
+    """Waves-per-SIMD targets of the compiled solver variants for a dtype."""
+    f32 = int(_f32(dtype))
+    L = _native.lib()
+    return [L.gamer_solver_variant_waves(f32, v) for v in range(L.gamer_solver_variants(f32))]

@@ -22,12 +22,14 @@ class PeriodicGrid:
     """A uniform periodic grid of gx x gy x gz groups, advanced on the GPU."""
 
     def __init__(self, state: torch.Tensor, gx: int, gy: int, gz: int, dh: float, gamma: float,
-                 cfl: float = 0.5, theta: float | None = None):
+                 cfl: float = 0.5, theta: float | None = None, variant: int | None = None,
+                 grid: int | None = None):
         if not state.is_cuda:
             raise ValueError("state must live on the GPU")
         self.gx, self.gy, self.gz = gx, gy, gz
         self.n = gx * gy * gz
         self.gamma, self.cfl, self.theta = gamma, cfl, theta
+        self.variant, self.grid = variant, grid
         dev, dt_ = state.device, state.dtype
         self.state = [state.contiguous().clone(), torch.empty_like(state)]
         self.cur = 0
@@ -50,7 +52,8 @@ class PeriodicGrid:
         dst = 1 - src
         hydro.pack_periodic(self.state[src], self.gx, self.gy, self.gz, out=self.padded)
         hydro.hydro_solve_batched(self.padded, None, self.dt_dev, self.dh_dev, self.gamma,
-                                  out=self.state[dst], group_stats=self.stats, theta=self.theta)
+                                  out=self.state[dst], group_stats=self.stats, theta=self.theta,
+                                  variant=self.variant, grid=self.grid)
         self.t_dev += self.dt_dev
         hydro.step_reduce(self.stats, None, self.dh_dev, self.cfl, dt_out=self.dt_dev,
                           totals_out=self.totals)

@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 17
+    assert len(names) == 19
     for n in names:
         assert hasattr(lib, n), n
         assert n in _native.SIGNATURES, n
@@ -37,8 +37,18 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_opts_struct_layout():
-    # gamer_opts holds one double
-    assert ctypes.sizeof(_native.GamerOpts) == 8
+    # gamer_opts: double theta, int32 variant, int32 grid
+    assert ctypes.sizeof(_native.GamerOpts) == 16
+    assert _native.GamerOpts.variant.offset == 8 and _native.GamerOpts.grid.offset == 12
+
+
+def test_solver_variants(lib):
+    for f32 in (0, 1):
+        n = lib.gamer_solver_variants(f32)
+        assert n >= 1
+        waves = [lib.gamer_solver_variant_waves(f32, v) for v in range(n)]
+        assert all(1 <= w <= 8 for w in waves)
+        assert lib.gamer_solver_variant_waves(f32, n) == 0
 
 
 def test_version(lib):
@@ -74,9 +84,16 @@ def test_batched_argument_errors(lib):
     assert f(P, 4, None, P, None, 1, 1.4, None, P, None, None) == _native.GAMER_EINVAL  # no dh_dev
     assert f(P, 4, None, P, P, 0, 1.4, None, P, None, None) == _native.GAMER_EINVAL
     assert f(P, 4, None, P, P, 33, 1.4, None, P, None, None) == _native.GAMER_EINVAL
-    bad = _native.GamerOpts(2.5)
+    bad = _native.GamerOpts(2.5, 0, 0)
     assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
-    bad = _native.GamerOpts(0.5)
+    bad = _native.GamerOpts(0.5, 0, 0)
+    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+    bad = _native.GamerOpts(1.5, 99, 0)
+    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+    assert b"variant" in lib.gamer_last_error()
+    bad = _native.GamerOpts(1.5, -1, 0)
+    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+    bad = _native.GamerOpts(1.5, 0, -4)
     assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
 
 

@@ -268,3 +268,40 @@ def test_workload2_full_size_fp64_and_fp32(gpu):
     ora32, _, _ = oracle.hydro_solve(oracle.pack_periodic(st.float().double().cpu().numpy(), 16, 16, 16),
                                      dt, dh, G53)
     close(out32, ora32, 1e-5, "workload 2 fp32")
+
+
+# ------------------------------------------------------------------ tuning variants
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_variants_and_grids_bitwise_equal(gpu, dtype):
+    """Every compiled solver variant, with one work-group per group or a
+    persistent grid, gives bitwise the same output and stats."""
+    st, dh = W.cosmo_like(n=48)
+    gp = hydro.pack_periodic(st.to(dtype).to(gpu), 3, 3, 3)
+    dt_dev = torch.tensor([2e-4], dtype=torch.float64, device=gpu)
+    dh_dev = torch.tensor([dh], dtype=torch.float64, device=gpu)
+    ref_out, ref_st = None, None
+    for v in range(len(hydro.solver_variants(dtype))):
+        for grid in (0, 1, 4, 13, 100):
+            stats = torch.empty((27, 8), dtype=torch.float64, device=gpu)
+            out = hydro.hydro_solve_batched(gp, None, dt_dev, dh_dev, G53, group_stats=stats,
+                                            variant=v, grid=grid)
+            torch.cuda.synchronize()
+            if ref_out is None:
+                ref_out, ref_st = out.clone(), stats.clone()
+            assert torch.equal(out, ref_out), (v, grid)
+            assert torch.equal(stats, ref_st), (v, grid)
+
+
+def test_autotune_picks_a_candidate(gpu, tmp_path, monkeypatch):
+    from paper_1007_3818_amd import autotune
+    monkeypatch.setenv("GAMER_TUNE_CACHE", str(tmp_path / "tune.json"))
+    st, dh = W.smooth_modes(n=64)
+    gp = hydro.pack_periodic(st.float().to(gpu), 4, 4, 4)
+    dt_dev = torch.tensor([1e-3], dtype=torch.float64, device=gpu)
+    dh_dev = torch.tensor([dh], dtype=torch.float64, device=gpu)
+    r = autotune.tune(gp, dt_dev, dh_dev, G53, reps=2)
+    assert (r["variant"], r["grid"]) in autotune.candidates(torch.float32, 64)
+    assert not r["cached"]
+    r2 = autotune.tune(gp, dt_dev, dh_dev, G53, reps=2)
+    assert r2["cached"] and r2["variant"] == r["variant"] and r2["grid"] == r["grid"]
