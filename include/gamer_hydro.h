@@ -174,8 +174,9 @@ int gamer_conserved_sums_f32(const float *groups, int64_t n_groups, double dh,
  * padded: [gx*gy*gz][5][20][20][20]; each padded cell takes the value of
  * the cell at its periodically wrapped global position.  The paper prepares
  * ghost zones on the host from the AMR hierarchy; this covers the uniform
- * periodic case on the device.  Errors: GAMER_EINVAL for gx, gy, gz < 1 or
- * gx*gy*gz*100 > INT32_MAX (about 21 million groups). */
+ * periodic case on the device.  Both arrays must be aligned to 4 elements
+ * (16 B float, 32 B double).  Errors: GAMER_EINVAL for gx, gy, gz < 1,
+ * gx*gy*gz*100 > INT32_MAX (about 21 million groups), NULL or misaligned arrays. */
 int gamer_pack_periodic(const double *state, int gx, int gy, int gz, double *padded);
 int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *padded);
 

@@ -166,6 +166,10 @@ int pack_common(const T *state, int gx, int gy, int gz, T *padded) {
     if (int64_t(gx) * gy * gz * NV * NP > INT32_MAX)
         return fail(GAMER_EINVAL, "grid too large (gx*gy*gz*100 must fit in int32)");
     if (!state || !padded) return fail(GAMER_EINVAL, "NULL state or padded");
+    // rows are moved with 4-element vector loads and stores
+    if (reinterpret_cast<uintptr_t>(state) % (4 * sizeof(T)) ||
+        reinterpret_cast<uintptr_t>(padded) % (4 * sizeof(T)))
+        return fail(GAMER_EINVAL, "state and padded must be aligned to 4 elements");
     return check_hip(launch_pack_periodic<T>(state, gx, gy, gz, padded, g_stream), "pack launch");
 }
 

@@ -7,31 +7,55 @@ namespace gamer {
 namespace {
 
 // ---- same-level periodic ghost fill --------------------------------------
-// One work-group per (group, variable, padded z-plane): 400 values, written by
-// consecutive threads along x; 32-bit index arithmetic only.
+// One thread per padded row of 20 values along x: the 16 interior values come
+// from one contiguous source row (vector loads), the two ghost values on each
+// side from the periodic x neighbours; the row is written with vector stores.
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using type = float4;
+};
+template <>
+struct Vec4<double> {
+    using type = double4;
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void pack_periodic_kernel(const T *__restrict__ state, int gx,
                                                             int gy, int gz, T *__restrict__ padded,
-                                                            int n_planes) {
-    const int NX = gx * NI, NY = gy * NI, NZ = gz * NI;
-    for (int b = blockIdx.x; b < n_planes; b += gridDim.x) {
-        const int kp = b % NP;
-        const int v = (b / NP) % NV;
-        const int g = b / (NP * NV);
+                                                            int64_t n_rows) {
+    using V = typename Vec4<T>::type;
+    const int NY = gy * NI, NZ = gz * NI;
+    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n_rows;
+         r += int64_t(gridDim.x) * blockDim.x) {
+        // r = ((g * 5 + v) * 20 + kp) * 20 + jp
+        const int jp = int(r % NP);
+        const int64_t r1 = r / NP;
+        const int kp = int(r1 % NP);
+        const int64_t r2 = r1 / NP;
+        const int v = int(r2 % NV);
+        const int g = int(r2 / NV);
         const int bx = g % gx, by = (g / gx) % gy, bz = g / (gx * gy);
-        int Z = bz * NI + kp - NG;
+        int Y = by * NI + jp - NG, Z = bz * NI + kp - NG;
+        Y = Y < 0 ? Y + NY : (Y >= NY ? Y - NY : Y);
         Z = Z < 0 ? Z + NZ : (Z >= NZ ? Z - NZ : Z);
-        const T *src_z = state + int64_t(gx) * gy * (Z / NI) * GOUT + v * (NI * NI * NI) +
-                         (Z % NI) * (NI * NI);
-        T *dst = padded + int64_t(b) * NPL;
-        for (int p = threadIdx.x; p < NPL; p += blockDim.x) {
-            const int ip = p % NP, jp = p / NP;
-            int X = bx * NI + ip - NG, Y = by * NI + jp - NG;
-            X = X < 0 ? X + NX : (X >= NX ? X - NX : X);
-            Y = Y < 0 ? Y + NY : (Y >= NY ? Y - NY : Y);
-            const int sg = X / NI + gx * (Y / NI);
-            dst[p] = src_z[int64_t(sg) * GOUT + (Y % NI) * NI + (X % NI)];
-        }
+        const int xl = bx == 0 ? gx - 1 : bx - 1, xr = bx == gx - 1 ? 0 : bx + 1;
+        const int64_t row = int64_t(gx) * (Y / NI + int64_t(gy) * (Z / NI));  // group of x block 0
+        const int64_t off = int64_t(v) * (NI * NI * NI) + (Z % NI) * (NI * NI) + (Y % NI) * NI;
+        const T *c = state + (row + bx) * GOUT + off;
+        const T *lft = state + (row + xl) * GOUT + off;
+        const T *rgt = state + (row + xr) * GOUT + off;
+        const V c0 = reinterpret_cast<const V *>(c)[0];
+        const V c1 = reinterpret_cast<const V *>(c)[1];
+        const V c2 = reinterpret_cast<const V *>(c)[2];
+        const V c3 = reinterpret_cast<const V *>(c)[3];
+        V *dst = reinterpret_cast<V *>(padded + r * NP);
+        dst[0] = V{lft[NI - 2], lft[NI - 1], c0.x, c0.y};
+        dst[1] = V{c0.z, c0.w, c1.x, c1.y};
+        dst[2] = V{c1.z, c1.w, c2.x, c2.y};
+        dst[3] = V{c2.z, c2.w, c3.x, c3.y};
+        dst[4] = V{c3.z, c3.w, rgt[0], rgt[1]};
     }
 }
 
@@ -94,21 +118,37 @@ __global__ __launch_bounds__(256) void group_stats_kernel(const T *__restrict__ 
 }
 
 // ---- fixed-order reduction of group stats ----------------------------------
-// One work-group of RT threads.  Thread t folds groups t, t+RT, ... in order,
-// then a fixed tree combines the threads; the result does not depend on timing.
+// One work-group of RT threads.  Thread t folds groups t, t+RT, ... in order;
+// each wave combines its lanes by a fixed shuffle tree and wave 0 combines the
+// waves in order.  The result does not depend on timing.
 constexpr int RT = 1024;
+constexpr int RW = RT / 64;
 
-__device__ double block_tree(double x, bool is_max, double *red) {
-    const int t = threadIdx.x;
-    red[t] = x;
-    __syncthreads();
-    for (int s = RT / 2; s >= 1; s >>= 1) {
-        if (t < s) red[t] = is_max ? fmax(red[t], red[t + s]) : red[t] + red[t + s];
-        __syncthreads();
+template <int N>
+__device__ void block_fold(double (&x)[N], const bool (&is_max)[N], double (*red)[RW]) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const double y = __shfl_down(x[q], off, 64);
+            x[q] = is_max[q] ? fmax(x[q], y) : x[q] + y;
+        }
     }
-    const double r = red[0];
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) red[q][wave] = x[q];
+    }
     __syncthreads();
-    return r;
+    if (t == 0) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            double a = red[q][0];
+            for (int w = 1; w < RW; ++w) a = is_max[q] ? fmax(a, red[q][w]) : a + red[q][w];
+            x[q] = a;
+        }
+    }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(RT) void reduce_kernel(const double *__restrict__ stats, int64_t n,
@@ -117,36 +157,40 @@ __global__ __launch_bounds__(RT) void reduce_kernel(const double *__restrict__ s
                                                     int n_levels, double cfl,
                                                     double *__restrict__ dt_out,
                                                     double *__restrict__ totals_out) {
-    __shared__ double red[RT];
+    __shared__ double red[7][RW];
     const int t = threadIdx.x;
-    if (dt_out) {
-        for (int L = 0; L < n_levels; ++L) {
-            double m = 0.0;
-            for (int64_t g = t; g < n; g += RT) {
-                const int lg = level ? int(level[g]) : 0;
-                if (lg == L) m = fmax(m, stats[g * NSTAT + 5]);
-            }
-            m = block_tree(m, true, red);
-            if (t == 0) {
-                const double h = dh_dev ? dh_dev[L] : dh;
-                dt_out[L] = m > 0.0 ? cfl * h / m : INFINITY;
-            }
+    if (totals_out) {
+        // stats 0..4 weighted by dh^3 of the group's level, then stats 6 and 7
+        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+        const bool sum7[7] = {false, false, false, false, false, false, false};
+        for (int64_t g = t; g < n; g += RT) {
+            const double h = dh_dev ? dh_dev[level ? int(level[g]) : 0] : dh;
+            const double w = h * h * h;
+            const double *st = stats + g * NSTAT;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) acc[q] += w * st[q];
+            acc[5] += st[6];
+            acc[6] += st[7];
+        }
+        block_fold(acc, sum7, red);
+        if (t == 0) {
+#pragma unroll
+            for (int q = 0; q < 7; ++q) totals_out[q] = acc[q];
         }
     }
-    if (totals_out) {
-        for (int q = 0; q < 7; ++q) {
-            const int src = q < 5 ? q : q + 1;  // stats 0..4, then 6, 7
-            double s = 0.0;
+    if (dt_out) {
+        const bool max1[1] = {true};
+        for (int L = 0; L < n_levels; ++L) {
+            double m[1] = {0.0};
             for (int64_t g = t; g < n; g += RT) {
-                double w = 1.0;
-                if (q < 5) {
-                    const double h = dh_dev ? dh_dev[level ? int(level[g]) : 0] : dh;
-                    w = h * h * h;
-                }
-                s += w * stats[g * NSTAT + src];
+                const int lg = level ? int(level[g]) : 0;
+                if (lg == L) m[0] = fmax(m[0], stats[g * NSTAT + 5]);
             }
-            s = block_tree(s, false, red);
-            if (t == 0) totals_out[q] = s;
+            block_fold(m, max1, red);
+            if (t == 0) {
+                const double hL = dh_dev ? dh_dev[L] : dh;
+                dt_out[L] = m[0] > 0.0 ? cfl * hL / m[0] : INFINITY;
+            }
         }
     }
 }
@@ -155,13 +199,13 @@ __global__ __launch_bounds__(RT) void reduce_kernel(const double *__restrict__ s
 
 template <typename T>
 hipError_t launch_pack_periodic(const T *state, int gx, int gy, int gz, T *padded, hipStream_t s) {
-    // n_planes = groups * 5 * 20 must fit in int (the ABI caps the group count)
-    const int64_t n_planes = int64_t(gx) * gy * gz * NV * NP;
-    if (n_planes == 0) return hipSuccess;
-    const int64_t cap = int64_t(256) * 1024;
-    const unsigned grid = unsigned(n_planes < cap ? n_planes : cap);
-    hipLaunchKernelGGL(pack_periodic_kernel<T>, dim3(grid), dim3(256), 0, s, state, gx, gy, gz,
-                       padded, int(n_planes));
+    const int64_t n_rows = int64_t(gx) * gy * gz * NV * NP * NP;
+    if (n_rows == 0) return hipSuccess;
+    int64_t blocks = (n_rows + 255) / 256;
+    const int64_t cap = int64_t(256) * 2048;
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(pack_periodic_kernel<T>, dim3(unsigned(blocks)), dim3(256), 0, s, state, gx,
+                       gy, gz, padded, n_rows);
     return hipGetLastError();
 }
 

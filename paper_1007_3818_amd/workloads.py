@@ -196,3 +196,17 @@ def sedov_level2_selection(n_root: int = 128, count: int = 20000):
     d2 = (bx + 0.5 - centre) ** 2 + (by + 0.5 - centre) ** 2 + (bz + 0.5 - centre) ** 2
     order = np.lexsort((idx, d2))
     return np.sort(order[:count])
+
+
+def sedov_amr(n_root: int = 128, count: int = 20000, gamma: float = GAMMA, device="cpu"):
+    """Workload 3: the three uniform levels of the Sedov blast and the level-2
+    groups kept in the batch.  Returns a list of (groups, dh, gx, ids) per level,
+    where ``ids`` are the group indices of that level that enter the batch (all
+    groups of levels 0 and 1, the ``count`` nearest the blast of level 2).  The
+    batch is levels 0, 1, 2 in that order; each level is periodic within itself."""
+    out = []
+    for level in range(3):
+        groups, dh, gx = sedov_level(level, n_root, gamma, device)
+        ids = (np.arange(gx ** 3) if level < 2 else sedov_level2_selection(n_root, count))
+        out.append((groups, dh, gx, ids))
+    return out

@@ -405,3 +405,12 @@ def test_exact_riemann_closed_forms():
     p, u, rl, rr = er.star_state((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), G53)
     assert er.sample((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), G53, u - 1e-9)[2] == pytest.approx(p)
     assert er.sample((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), G53, u + 1e-9)[2] == pytest.approx(p)
+
+
+def test_pack_subset_equals_full_pack():
+    r = np.random.default_rng(10)
+    gx, gy, gz = 3, 2, 2
+    st = r.standard_normal((gx * gy * gz, 5, 16, 16, 16))
+    full = oracle.pack_periodic(st, gx, gy, gz)
+    ids = [0, 5, 11, 7]
+    assert np.array_equal(oracle.pack_periodic_subset(st, gx, gy, gz, ids), full[ids])
