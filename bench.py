@@ -131,7 +131,8 @@ def bench_dtype(tag, state, g, dh, steps, warmup):
         "unit": "TFLOP/s",
         "frac": flops / (k_ms * 1e-3) / PEAK[tag],
         "traffic": traffic,
-        "kernel": f"solve_kernel<{'float' if tag == 'f32' else 'double'}>",
+        "kernel": "solve_kernel<%s, %d, %d>" % (("float" if tag == "f32" else "double"),
+                                                *hydro.solver_variants(padded.dtype)[variant]),
         "kernel_ms": k_ms,
         "flops_per_cell": FLOPS_PER_CELL,
         "algorithmic_bytes_per_cell": bytes_per_group(elem) / CELLS,
@@ -168,7 +169,8 @@ def bench_dtype(tag, state, g, dh, steps, warmup):
         "roofline": roof,
         "fallbacks": [int(tot[5]), int(tot[6])],
         "dt": dt_used,
-        "tuning": {"variant": variant, "waves_per_simd": hydro.solver_variants(padded.dtype)[variant],
+        "tuning": {"variant": variant, "threads": hydro.solver_variants(padded.dtype)[variant][0],
+                   "waves_per_simd": hydro.solver_variants(padded.dtype)[variant][1],
                    "grid": grid, "candidates": tuned["table"]},
         "with_ghost_fill": {"ms_per_step": ms_full, "cell_updates_per_s": cells / (ms_full * 1e-3),
                             "step": "periodic ghost fill + batched solve + reduce, grid evolving"},

@@ -68,8 +68,9 @@ typedef struct gamer_opts {
      * (1: minmod, 2: monotonised central); 0 selects the default 1.5. */
     double theta;
     /* Compiled solver variant, 0 .. gamer_solver_variants(f32)-1 (0 is the
-     * default).  Variants differ only in the register budget they were built
-     * for (waves per SIMD); their results are bitwise identical. */
+     * default).  Variants differ in work-group size and in the register budget
+     * they were built for (waves per SIMD); their results are bitwise
+     * identical. */
     int32_t variant;
     /* Work-groups launched: 0 launches one per group; g > 0 launches
      * min(g, n_groups) persistent work-groups that stride over the groups. */
@@ -77,10 +78,11 @@ typedef struct gamer_opts {
 } gamer_opts;
 
 /* Number of compiled solver variants for the float (f32 != 0) or double path,
- * and the waves per SIMD variant v was built for (0 for an unknown v).  Used by
- * the tuner that picks a variant and a grid for a given batch. */
+ * and the shape of variant v: work-group size in threads and the waves per
+ * SIMD its register allocation allows (GAMER_EINVAL for an unknown v).  Used
+ * by the tuner that picks a variant and a grid for a given batch. */
 int gamer_solver_variants(int f32);
-int gamer_solver_variant_waves(int f32, int variant);
+int gamer_solver_variant_shape(int f32, int variant, int *threads, int *waves_per_simd);
 
 /* Library version, major * 10000 + minor * 100 + patch. */
 int gamer_version(void);

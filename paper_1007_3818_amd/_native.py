@@ -35,7 +35,7 @@ SIGNATURES = {
     "gamer_get_stream": (_P, []),
     "gamer_last_error": (ctypes.c_char_p, []),
     "gamer_solver_variants": (_I, [_I]),
-    "gamer_solver_variant_waves": (_I, [_I, _I]),
+    "gamer_solver_variant_shape": (_I, [_I, _I, _P, _P]),
     "gamer_hydro_solve": (_I, [_P, _I64, _D, _D, _D, _P, _P]),
     "gamer_hydro_solve_f32": (_I, [_P, _I64, _D, _D, _D, _P, _P]),
     "gamer_hydro_solve_batched": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO]),

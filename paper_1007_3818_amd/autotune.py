@@ -1,9 +1,11 @@
 """Launch-shape tuner for the batched solver.
 
 For a given batch (precision, group count) it times every compiled solver
-variant (register budget / waves per SIMD) with one work-group per group and
+variant (work-group size, register budget) with one work-group per group and
 with persistent grids of 1-4 work-groups per CU, checks that all candidates
-produce bitwise-identical output, and returns (and caches) the fastest.
+agree with the first to rounding (the compiler may contract to FMA
+differently under different register budgets; each variant is deterministic),
+and returns (and caches) the fastest.
 
 The cache is a JSON file keyed by device name, precision and the group count
 rounded up to a power of two; ``GAMER_TUNE_CACHE`` overrides its path.
@@ -32,6 +34,7 @@ def _key(dtype, n_groups: int) -> str:
 def candidates(dtype, n_groups: int):
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     grids = [0] + [n_cu * k for k in (1, 2, 3, 4) if n_cu * k < n_groups]
+    # compiled variants x grids
     return [(v, g) for v in range(len(hydro.solver_variants(dtype))) for g in grids]
 
 
@@ -55,6 +58,17 @@ def _save(table):
         pass  # an unwritable cache only costs re-tuning
 
 
+def max_rel_diff(a: torch.Tensor, b: torch.Tensor) -> float:
+    """max |a - b| / (|b| + max over the batch of |b| per variable)."""
+    a, b = a.double(), b.double()
+    scale = b.abs().amax(dim=(0, 2, 3, 4), keepdim=True)
+    den = b.abs() + scale
+    diff = (a - b).abs()
+    rel = torch.where(den > 0, diff / torch.where(den > 0, den, torch.ones_like(den)),
+                      torch.where(diff > 0, torch.full_like(diff, float("inf")), torch.zeros_like(diff)))
+    return float(rel.max())
+
+
 def tune(padded: torch.Tensor, dt_dev: torch.Tensor, dh_dev: torch.Tensor, gamma: float,
          level=None, reps: int = 5, use_cache: bool = True) -> dict:
     """Return {"variant", "grid", "ms", "table"} for this batch."""
@@ -72,15 +86,19 @@ def tune(padded: torch.Tensor, dt_dev: torch.Tensor, dh_dev: torch.Tensor, gamma
         torch.cuda.synchronize()
         if ref is None:
             ref = out.clone()
-        elif not torch.equal(out, ref):
-            raise RuntimeError(f"solver variant {v} grid {g} differs from variant 0: refusing to tune")
+        else:
+            err = max_rel_diff(out, ref)
+            if not err <= (1e-6 if padded.dtype == torch.float32 else 1e-13):
+                raise RuntimeError(f"solver variant {v} grid {g} differs from variant 0 by {err:.3e}: "
+                                   "refusing to tune")
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         ev[0].record()
         for _ in range(reps):
             hydro.hydro_solve_batched(padded, level, dt_dev, dh_dev, gamma, out=out, variant=v, grid=g)
         ev[1].record()
         torch.cuda.synchronize()
-        table.append({"variant": v, "waves_per_simd": hydro.solver_variants(padded.dtype)[v],
+        th, wv = hydro.solver_variants(padded.dtype)[v]
+        table.append({"variant": v, "threads": th, "waves_per_simd": wv,
                       "grid": g, "ms": ev[0].elapsed_time(ev[1]) / reps})
     best = min(table, key=lambda r: r["ms"])
     result = {"variant": best["variant"], "grid": best["grid"], "ms": best["ms"], "table": table}

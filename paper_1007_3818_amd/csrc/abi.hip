@@ -202,8 +202,12 @@ int gamer_solver_variants(int f32) {
     return f32 ? solve_variant_count<float>() : solve_variant_count<double>();
 }
 
-int gamer_solver_variant_waves(int f32, int variant) {
-    return f32 ? solve_variant_waves<float>(variant) : solve_variant_waves<double>(variant);
+int gamer_solver_variant_shape(int f32, int variant, int *threads, int *waves_per_simd) {
+    g_err[0] = 0;
+    if (!threads || !waves_per_simd) return fail(GAMER_EINVAL, "NULL output");
+    const int ok = f32 ? solve_variant_shape<float>(variant, threads, waves_per_simd)
+                       : solve_variant_shape<double>(variant, threads, waves_per_simd);
+    return ok ? GAMER_OK : fail(GAMER_EINVAL, "no variant %d", variant);
 }
 
 int gamer_hydro_solve(const double *groups_in, int64_t n_groups, double dt, double dh,

@@ -34,11 +34,11 @@ struct SolveParams {
     int64_t n_groups;
 };
 
-// Compiled solver variants (occupancy targets) and the launcher.
+// Compiled solver variants (work-group size, occupancy target) and the launcher.
 template <typename T>
 int solve_variant_count();
 template <typename T>
-int solve_variant_waves(int variant);
+int solve_variant_shape(int variant, int *threads, int *waves_per_simd);
 template <typename T>
 hipError_t launch_solve(const SolveParams<T> &p, int variant, int64_t grid, hipStream_t s);
 

@@ -5,13 +5,14 @@
 // details follow Toro (2009) Sec. 14.4 and Sec. 11.2, the sources the paper
 // cites; see include/gamer_hydro.h for the interface.
 //
-// Kernel design (one work-group of 320 threads = 5 wave64s per group):
+// Kernel design (one work-group per group at a time):
 //  - The group is swept in z.  At sweep position k the work-group holds the
 //    primitive variables of planes k-1, k, k+1 (20 x 20 each) in a three-slot
-//    LDS ring, and each thread owns one cell of the face-state plane: threads
-//    0..255 the 16 x 16 interior columns, threads 256..319 the 64 ghost cells
-//    just outside the four side faces (the face states of those cells are
-//    needed by the group's boundary faces).
+//    LDS ring.  Threads 0..255 own the 16 x 16 interior columns.  The 64 ghost
+//    cells just outside the four side faces (whose face states the group's
+//    boundary faces need) are computed either by 64 extra threads (320-thread
+//    shape, 5 waves) or, in the 256-thread shape (one wave per SIMD), by one
+//    wave in a second round, rotating over the waves plane by plane.
 //  - A thread computes its cell's limited slopes in x, y, z from the LDS ring,
 //    the half-step increment, and its predicted face states.  States that a
 //    neighbour needs (the +x and +y faces) go to LDS; the -x, -y, -z and +z
@@ -30,7 +31,6 @@
 namespace gamer {
 namespace {
 
-constexpr int NTHR = 320;
 constexpr int NINNER = NI * NI;  // 256 interior columns
 
 template <typename T>
@@ -42,15 +42,27 @@ struct alignas(16) Lds {
 };
 
 template <typename T>
-__device__ __forceinline__ T limiter(T a, T b, T theta) {
-    // generalised minmod: 0 at extrema, else sign(a) min(theta|a|, theta|b|, |a+b|/2)
-    if (a * b <= T(0)) return T(0);
-    T m = fmin(theta * fabs(a), fmin(theta * fabs(b), T(0.5) * fabs(a + b)));
-    return a > T(0) ? m : -m;
+__device__ __forceinline__ bool physical(const T u[NV]) {
+    // rho > 0 and p > 0  <=>  rho > 0 and 2 rho E > |m|^2
+    return u[0] > T(0) && T(2) * u[0] * u[4] > u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
 }
 
-// Physical flux along direction D of primitive state (rho, u_x, u_y, u_z, p);
-// writes F.
+// Generalised minmod: 0 at extrema (a b <= 0), else sign(a) min(theta|a|,
+// theta|b|, |a+b|/2).  In float it is evaluated as med3(theta a,
+// med3(theta b, (a+b)/2, 0), 0): the median with 0 is the two-argument minmod,
+// and nesting it gives the same value bitwise whenever a and b share a sign
+// (and 0 otherwise); only an a b that underflows to 0 would differ.
+__device__ __forceinline__ float limiter(float a, float b, float theta) {
+    const float inner = __builtin_amdgcn_fmed3f(theta * b, 0.5f * (a + b), 0.0f);
+    return __builtin_amdgcn_fmed3f(theta * a, inner, 0.0f);
+}
+__device__ __forceinline__ double limiter(double a, double b, double theta) {
+    if (a * b <= 0.0) return 0.0;
+    const double m = fmin(theta * fabs(a), fmin(theta * fabs(b), 0.5 * fabs(a + b)));
+    return a > 0.0 ? m : -m;
+}
+
+// Physical flux along direction D of a primitive state (rho, u_x, u_y, u_z, p).
 template <int D, typename T>
 __device__ __forceinline__ void flux_prim(const T w[NV], const Consts<T> &c, T f[NV]) {
     const T un = w[1 + D];
@@ -64,6 +76,7 @@ __device__ __forceinline__ void flux_prim(const T w[NV], const Consts<T> &c, T f
     f[4] = (e + w[4]) * un;
 }
 
+// Conserved variables of a primitive state.
 template <typename T>
 __device__ __forceinline__ void cons_prim(const T w[NV], const Consts<T> &c, T u[NV]) {
     u[0] = w[0];
@@ -73,11 +86,53 @@ __device__ __forceinline__ void cons_prim(const T w[NV], const Consts<T> &c, T u
     u[4] = w[4] * c.igm1 + c.half * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
 }
 
-template <typename T>
-__device__ __forceinline__ bool physical(const T u[NV]) {
-    // rho > 0 and p > 0  <=>  rho > 0 and 2 rho E > |m|^2
-    return u[0] > T(0) && T(2) * u[0] * u[4] > u[1] * u[1] + u[2] * u[2] + u[3] * u[3];
+// S += F_D(W0 - dW/2) - F_D(W0 + dW/2)
+template <int D, typename T>
+__device__ __forceinline__ void flux_difference(const T W0[NV], const T dw[NV], const Consts<T> &c,
+                                                T Sv[NV]) {
+    T wm[NV], wp[NV], fm[NV], fp[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        wm[v] = W0[v] - c.half * dw[v];
+        wp[v] = W0[v] + c.half * dw[v];
+    }
+    flux_prim<D>(wm, c, fm);
+    flux_prim<D>(wp, c, fp);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Sv[v] += fm[v] - fp[v];
 }
+
+// Half-step prediction of one cell (conservative Hancock step, all three
+// directions): face values W0 -+ dW_d/2, the common increment
+//   S = dt/(2dh) sum_d [F_d(W0 - dW_d/2) - F_d(W0 + dW_d/2)],
+// and Ub[d][0] (minus face), Ub[d][1] (plus face) = cons(W0 -+ dW_d/2) + S.
+// Returns false if any of the six has rho <= 0 or p <= 0.
+template <typename T>
+__device__ __forceinline__ bool predict(const T W0[NV], const T dW[3][NV], T hdt,
+                                        const Consts<T> &c, T Ub[3][2][NV]) {
+    T Sv[NV] = {T(0), T(0), T(0), T(0), T(0)};
+    flux_difference<0>(W0, dW[0], c, Sv);
+    flux_difference<1>(W0, dW[1], c, Sv);
+    flux_difference<2>(W0, dW[2], c, Sv);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Sv[v] *= hdt;
+    bool ok = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            T wf[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) wf[v] = W0[v] + T(side ? 1 : -1) * (c.half * dW[d][v]);
+            cons_prim(wf, c, Ub[d][side]);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Ub[d][side][v] += Sv[v];
+            ok = ok && physical(Ub[d][side]);
+        }
+    }
+    return ok;
+}
+
 
 // Physical flux of a rotated conserved state (normal = component 1), given
 // its normal velocity and pressure.
@@ -247,49 +302,58 @@ __device__ __forceinline__ void block_reduce_stats(double st[NSTAT], double *red
     __syncthreads();
 }
 
-// Variants: the waves per SIMD that the register allocation must allow.  LDS
-// allows three 5-wave float work-groups per CU (45 KB each) and two double
-// ones (80 KB each); more waves trade registers for spills.  The first entry
-// of each list is the default; the tuner may pick another at run time.
+// Compiled variants: work-group size (320: ghost-layer cells on their own wave;
+// 256: one wave per SIMD, ghost-layer cells as a second round) and the waves
+// per SIMD the register allocation must allow.  LDS allows three float
+// work-groups per CU (45 KB each) and two double ones (80 KB each).  The first
+// entry of each list is the default; the tuner may pick another at run time.
+struct Shape {
+    int threads, waves;
+};
 template <typename T>
 struct Variants;
 template <>
 struct Variants<float> {
-    static constexpr int count = 2;
-    static constexpr int waves[count] = {4, 3};
+    static constexpr int count = 3;
+    static constexpr Shape shape[count] = {{256, 3}, {320, 4}, {320, 3}};
 };
 template <>
 struct Variants<double> {
     static constexpr int count = 2;
-    static constexpr int waves[count] = {2, 3};
+    static constexpr Shape shape[count] = {{256, 2}, {320, 2}};
 };
 
-template <typename T, int WAVES>
-__global__ __launch_bounds__(NTHR, WAVES) void solve_kernel(SolveParams<T> P) {
+// The 64 cells of the ghost layer just outside the four side faces of a plane,
+// numbered r = 0..63: -x layer (gives the +x state of face 0), +x layer (solves
+// x face 16), -y layer, +y layer.
+__device__ __forceinline__ void ring_cell(int r, int &ci, int &cj) {
+    const int q = r & 15;
+    switch (r >> 4) {
+        case 0: ci = -1; cj = q; break;
+        case 1: ci = NI; cj = q; break;
+        case 2: ci = q; cj = -1; break;
+        default: ci = q; cj = NI; break;
+    }
+}
+
+// One work-group of NT threads advances one group at a time (grid-stride).
+//  NT = 320: threads 0..255 own the interior columns, 256..319 the ghost-layer
+//            cells of every plane (5 waves).
+//  NT = 256: threads own the interior columns; in plane k the wave k mod 4 also
+//            computes the 64 ghost-layer cells in a second round (4 waves, one
+//            per SIMD).
+template <typename T, int NT, int WAVES>
+__global__ __attribute__((amdgpu_flat_work_group_size(NT, NT), amdgpu_waves_per_eu(WAVES, 8)))
+void solve_kernel(SolveParams<T> P) {
+    static_assert(NT == 320 || NT == 256, "work-group shape");
+    constexpr bool SPLIT = NT == 320;
     __shared__ Lds<T> S;
     const int t = threadIdx.x;
+    const int wave = t >> 6;
 
-    // ---- this thread's cell in the face-state plane ----
     const bool inner = t < NINNER;
-    int ci, cj;
-    if (inner) {
-        ci = t & 15;
-        cj = t >> 4;
-    } else {
-        const int r = t - NINNER, q = r & 15;
-        switch (r >> 4) {
-            case 0: ci = -1; cj = q; break;   // -x ghost layer: gives +x state of face 0
-            case 1: ci = NI; cj = q; break;   // +x ghost layer: solves x face 16
-            case 2: ci = q; cj = -1; break;   // -y ghost layer
-            default: ci = q; cj = NI; break;  // +y ghost layer
-        }
-    }
-    const int pos = (cj + NG) * NP + (ci + NG);
-    // roles within the plane (k = 0..15)
-    const bool put_xp = ci <= NI - 1 && cj >= 0 && cj < NI;  // +x state feeds face ci+1
-    const bool put_yp = cj <= NI - 1 && ci >= 0 && ci < NI;  // +y state feeds face cj+1
-    const bool do_x = ci >= 0 && cj >= 0 && cj < NI;          // solves x face ci
-    const bool do_y = cj >= 0 && ci >= 0 && ci < NI;          // solves y face cj
+    const int ii = t & 15, jj = t >> 4;  // interior column of threads 0..255
+    const int my_ring = SPLIT ? t - NINNER : (t & 63);
 
     const Consts<T> c = make_consts<T>(P.gamma, P.theta);
 
@@ -301,11 +365,10 @@ __global__ __launch_bounds__(NTHR, WAVES) void solve_kernel(SolveParams<T> P) {
             dh = P.dh_dev[lev];
         }
         const double dtdh = dt / dh;
-        const T hdt = T(0.5 * dtdh);
         const T *__restrict__ in = P.in + g * GIN;
 
-        // ---- load helpers: positions t and t + NTHR of a padded plane ----
-        const int p0 = t, p1 = t + NTHR;
+        // ---- load helpers: positions t and t + NT of a padded plane ----
+        const int p0 = t, p1 = t + NT;
         const bool has1 = p1 < NPL;
         T pre0[NV], pre1[NV];
         auto fetch = [&](int plane) {  // plane in -2..17
@@ -363,12 +426,28 @@ __global__ __launch_bounds__(NTHR, WAVES) void solve_kernel(SolveParams<T> P) {
             __syncthreads();  // B1: plane k+1 visible; planes k-1, k, k+1 in the ring
 
             const bool edge = (k < 0 || k >= NI);
-            const bool active = inner || !edge;
-            T xm[NV], ym[NV], zm[NV], zpn[NV];
-            if (active) {
-                const T(*wm)[NPL] = S.w[(k + 2) % 3];
-                const T(*w0)[NPL] = S.w[(k + 3) % 3];
-                const T(*wq)[NPL] = S.w[(k + 4) % 3];
+            // ghost-layer cell of this thread in this plane (-1: none)
+            const int ring = edge ? -1 : (SPLIT ? my_ring : (wave == (k & 3) ? my_ring : -1));
+
+            // ---- face states: the interior cell, then the ghost-layer cell ----
+            // (one code path for both, so a face state is computed identically
+            // wherever its cell sits)
+            T xm[NV], ym[NV], zm[NV], zpn[NV], rs[NV];  // rs: kept state of a ghost-layer cell
+            const T(*wm)[NPL] = S.w[(k + 2) % 3];
+            const T(*w0)[NPL] = S.w[(k + 3) % 3];
+            const T(*wq)[NPL] = S.w[(k + 4) % 3];
+#pragma unroll 1
+            for (int round = 0; round < 2; ++round) {
+                int ci, cj;
+                if (round == 0) {
+                    if (!inner) continue;
+                    ci = ii;
+                    cj = jj;
+                } else {
+                    if (ring < 0) continue;
+                    ring_cell(ring, ci, cj);
+                }
+                const int pos = (cj + NG) * NP + (ci + NG);
                 T W0[NV], dW[3][NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
@@ -378,76 +457,51 @@ __global__ __launch_bounds__(NTHR, WAVES) void solve_kernel(SolveParams<T> P) {
                     dW[1][v] = limiter(q0 - w0[v][pos - NP], w0[v][pos + NP] - q0, c.theta);
                     dW[2][v] = limiter(q0 - wm[v][pos], wq[v][pos] - q0, c.theta);
                 }
-                // half-step increment S = dt/(2dh) sum_d [F_d(W^{d,-}) - F_d(W^{d,+})]
-                T Sv[NV] = {T(0), T(0), T(0), T(0), T(0)};
-                {
-                    T wmf[NV], wpf[NV], fm[NV], fp[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        wmf[v] = W0[v] - c.half * dW[0][v];
-                        wpf[v] = W0[v] + c.half * dW[0][v];
-                    }
-                    flux_prim<0>(wmf, c, fm);
-                    flux_prim<0>(wpf, c, fp);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) Sv[v] += fm[v] - fp[v];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        wmf[v] = W0[v] - c.half * dW[1][v];
-                        wpf[v] = W0[v] + c.half * dW[1][v];
-                    }
-                    flux_prim<1>(wmf, c, fm);
-                    flux_prim<1>(wpf, c, fp);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) Sv[v] += fm[v] - fp[v];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        wmf[v] = W0[v] - c.half * dW[2][v];
-                        wpf[v] = W0[v] + c.half * dW[2][v];
-                    }
-                    flux_prim<2>(wmf, c, fm);
-                    flux_prim<2>(wpf, c, fp);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) Sv[v] += fm[v] - fp[v];
-                }
-#pragma unroll
-                for (int v = 0; v < NV; ++v) Sv[v] *= hdt;
-
                 // predicted face states Ubar^{d,+-} = cons(W0 +- dW_d/2) + S
-                bool ok = true;
-                T xp[NV], yp[NV];
-                auto face = [&](const T dw[NV], T sgn, T out[NV]) {
-                    T wf[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) wf[v] = W0[v] + sgn * (c.half * dw[v]);
-                    cons_prim(wf, c, out);
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) out[v] += Sv[v];
-                    ok = ok && physical(out);
-                };
-                face(dW[0], T(-1), xm);
-                face(dW[0], T(1), xp);
-                face(dW[1], T(-1), ym);
-                face(dW[1], T(1), yp);
-                face(dW[2], T(-1), zm);
-                face(dW[2], T(1), zpn);
-                if (!ok) {
+                T Ub[3][2][NV];
+                if (!predict(W0, dW, T(0.5 * dtdh), c, Ub)) {
                     // first-order fallback: every face of the cell takes the cell average
                     ++n_pred;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         const T u0 = in[v * NP * NPL + (k + NG) * NPL + pos];
-                        xm[v] = xp[v] = ym[v] = yp[v] = zm[v] = zpn[v] = u0;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) Ub[d][0][v] = Ub[d][1][v] = u0;
                     }
                 }
-                if (!edge) {
-                    if (put_xp) {
+                if (round == 0) {
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) S.sx[v][cj][ci + 1] = xp[v];
+                    for (int v = 0; v < NV; ++v) {
+                        xm[v] = Ub[0][0][v];
+                        ym[v] = Ub[1][0][v];
+                        zm[v] = Ub[2][0][v];
+                        zpn[v] = Ub[2][1][v];
                     }
-                    if (put_yp) {
+                    if (!edge) {
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) S.sy[v][cj + 1][ci] = yp[v];
+                        for (int v = 0; v < NV; ++v) {
+                            S.sx[v][cj][ci + 1] = Ub[0][1][v];
+                            S.sy[v][cj + 1][ci] = Ub[1][1][v];
+                        }
+                    }
+                } else {
+                    switch (ring >> 4) {
+                        case 0:  // +x state of face 0
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) S.sx[v][cj][0] = Ub[0][1][v];
+                            break;
+                        case 1:  // -x state of face 16, kept
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) rs[v] = Ub[0][0][v];
+                            break;
+                        case 2:  // +y state of face 0
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) S.sy[v][0][ci] = Ub[1][1][v];
+                            break;
+                        default:  // -y state of face 16, kept
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) rs[v] = Ub[1][0][v];
+                            break;
                     }
                 }
             }
@@ -457,7 +511,7 @@ __global__ __launch_bounds__(NTHR, WAVES) void solve_kernel(SolveParams<T> P) {
             if (inner && k >= 0) {
                 n_roe += roe_dir<2>(zp, zm, c, fzn);
                 if (P.flux && (k & 7) == 0) {
-                    T *dst = P.flux + g * GFLX + ((2 * 3 + (k >> 3)) * NV) * NINNER + cj * NI + ci;
+                    T *dst = P.flux + g * GFLX + ((2 * 3 + (k >> 3)) * NV) * NINNER + jj * NI + ii;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) dst[v * NINNER] = fzn[v];
                 }
@@ -465,28 +519,64 @@ __global__ __launch_bounds__(NTHR, WAVES) void solve_kernel(SolveParams<T> P) {
             __syncthreads();  // B2: +x / +y states visible
 
             if (!edge) {
-                if (do_x) {
-                    T UL[NV], F[NV];
+                // x faces: face ci of each interior cell, then face 16 of each row
+#pragma unroll 1
+                for (int round = 0; round < 2; ++round) {
+                    int row, f;
+                    const T *R;
+                    if (round == 0) {
+                        if (!inner) continue;
+                        row = jj;
+                        f = ii;
+                        R = xm;
+                    } else {
+                        if (ring < 0 || (ring >> 4) != 1) continue;
+                        row = ring & 15;
+                        f = NI;
+                        R = rs;
+                    }
+                    T UL[NV], UR[NV], F[NV];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) UL[v] = S.sx[v][cj][ci];
-                    n_roe += roe_dir<0>(UL, xm, c, F);
+                    for (int v = 0; v < NV; ++v) {
+                        UL[v] = S.sx[v][row][f];
+                        UR[v] = R[v];
+                    }
+                    n_roe += roe_dir<0>(UL, UR, c, F);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) S.sx[v][cj][ci] = F[v];
-                    if (P.flux && (ci & 7) == 0) {
-                        T *dst = P.flux + g * GFLX + ((0 * 3 + (ci >> 3)) * NV) * NINNER + k * NI + cj;
+                    for (int v = 0; v < NV; ++v) S.sx[v][row][f] = F[v];
+                    if (P.flux && (f & 7) == 0) {
+                        T *dst = P.flux + g * GFLX + ((0 * 3 + (f >> 3)) * NV) * NINNER + k * NI + row;
 #pragma unroll
                         for (int v = 0; v < NV; ++v) dst[v * NINNER] = F[v];
                     }
                 }
-                if (do_y) {
-                    T UL[NV], F[NV];
+                // y faces: face cj of each interior cell, then face 16 of each column
+#pragma unroll 1
+                for (int round = 0; round < 2; ++round) {
+                    int col, f;
+                    const T *R;
+                    if (round == 0) {
+                        if (!inner) continue;
+                        col = ii;
+                        f = jj;
+                        R = ym;
+                    } else {
+                        if (ring < 0 || (ring >> 4) != 3) continue;
+                        col = ring & 15;
+                        f = NI;
+                        R = rs;
+                    }
+                    T UL[NV], UR[NV], F[NV];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) UL[v] = S.sy[v][cj][ci];
-                    n_roe += roe_dir<1>(UL, ym, c, F);
+                    for (int v = 0; v < NV; ++v) {
+                        UL[v] = S.sy[v][f][col];
+                        UR[v] = R[v];
+                    }
+                    n_roe += roe_dir<1>(UL, UR, c, F);
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) S.sy[v][cj][ci] = F[v];
-                    if (P.flux && (cj & 7) == 0) {
-                        T *dst = P.flux + g * GFLX + ((1 * 3 + (cj >> 3)) * NV) * NINNER + k * NI + ci;
+                    for (int v = 0; v < NV; ++v) S.sy[v][f][col] = F[v];
+                    if (P.flux && (f & 7) == 0) {
+                        T *dst = P.flux + g * GFLX + ((1 * 3 + (f >> 3)) * NV) * NINNER + k * NI + col;
 #pragma unroll
                         for (int v = 0; v < NV; ++v) dst[v * NINNER] = F[v];
                     }
@@ -498,8 +588,8 @@ __global__ __launch_bounds__(NTHR, WAVES) void solve_kernel(SolveParams<T> P) {
                 if (k >= 1) {
                     // plane k-1 is complete: U - dt/dh ((dF_x + dF_y) + dF_z)
                     const int kk = k - 1;
-                    T *dst = P.out + g * GOUT + kk * NINNER + cj * NI + ci;
-                    const T *src = in + (kk + NG) * NPL + pos;
+                    T *dst = P.out + g * GOUT + kk * NINNER + t;
+                    const T *src = in + (kk + NG) * NPL + (jj + NG) * NP + (ii + NG);
                     T un[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
@@ -515,8 +605,8 @@ __global__ __launch_bounds__(NTHR, WAVES) void solve_kernel(SolveParams<T> P) {
                 if (!edge) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
-                        S.dxy[v][t] = (double(S.sx[v][cj][ci + 1]) - double(S.sx[v][cj][ci])) +
-                                      (double(S.sy[v][cj + 1][ci]) - double(S.sy[v][cj][ci]));
+                        S.dxy[v][t] = (double(S.sx[v][jj][ii + 1]) - double(S.sx[v][jj][ii])) +
+                                      (double(S.sy[v][jj + 1][ii]) - double(S.sy[v][jj][ii]));
                 }
                 if (k >= 0) {
 #pragma unroll
@@ -531,15 +621,15 @@ __global__ __launch_bounds__(NTHR, WAVES) void solve_kernel(SolveParams<T> P) {
             double all[NSTAT] = {st[0], st[1], st[2], st[3], st[4], st[5], double(n_pred),
                                  double(n_roe)};
             // S.w is free now (B3 of the last step passed); reuse it for the reduction
-            block_reduce_stats<NTHR>(all, reinterpret_cast<double *>(&S.w[0][0][0]),
-                                     P.stats + g * NSTAT);
+            block_reduce_stats<NT>(all, reinterpret_cast<double *>(&S.w[0][0][0]),
+                                   P.stats + g * NSTAT);
         } else {
             __syncthreads();
         }
     }
 }
 
-static_assert(sizeof(Lds<float>::w) >= NTHR * NSTAT * sizeof(double),
+static_assert(sizeof(Lds<float>::w) >= 320 * NSTAT * sizeof(double),
               "stats reduction must fit in the primitive ring");
 
 }  // namespace
@@ -550,9 +640,20 @@ int solve_variant_count() {
 }
 
 template <typename T>
-int solve_variant_waves(int v) {
-    return (v >= 0 && v < Variants<T>::count) ? Variants<T>::waves[v] : 0;
+int solve_variant_shape(int v, int *threads, int *waves) {
+    if (v < 0 || v >= Variants<T>::count) return 0;
+    *threads = Variants<T>::shape[v].threads;
+    *waves = Variants<T>::shape[v].waves;
+    return 1;
 }
+
+namespace {
+template <typename T, int V>
+void launch_variant(const SolveParams<T> &p, dim3 blocks, hipStream_t s) {
+    constexpr Shape sh = Variants<T>::shape[V];
+    hipLaunchKernelGGL((solve_kernel<T, sh.threads, sh.waves>), blocks, dim3(sh.threads), 0, s, p);
+}
+}  // namespace
 
 // variant < 0 selects the default; grid <= 0 launches one work-group per group,
 // grid > 0 a persistent grid that strides over the groups.
@@ -562,24 +663,25 @@ hipError_t launch_solve(const SolveParams<T> &p, int variant, int64_t grid, hipS
     const int64_t max_grid = int64_t(1) << 30;
     int64_t g = grid > 0 ? (grid < p.n_groups ? grid : p.n_groups) : p.n_groups;
     if (g > max_grid) g = max_grid;
-    const dim3 blocks = dim3(unsigned(g)), threads = dim3(NTHR);
+    const dim3 blocks = dim3(unsigned(g));
     switch (variant < 0 ? 0 : variant) {
-        case 0:
-            hipLaunchKernelGGL((solve_kernel<T, Variants<T>::waves[0]>), blocks, threads, 0, s, p);
-            break;
-        case 1:
-            hipLaunchKernelGGL((solve_kernel<T, Variants<T>::waves[1]>), blocks, threads, 0, s, p);
-            break;
-        default:
+        case 0: launch_variant<T, 0>(p, blocks, s); break;
+        case 1: launch_variant<T, 1>(p, blocks, s); break;
+        case 2:
+            if constexpr (Variants<T>::count > 2) {
+                launch_variant<T, 2>(p, blocks, s);
+                break;
+            }
             return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template int solve_variant_count<float>();
 template int solve_variant_count<double>();
-template int solve_variant_waves<float>(int);
-template int solve_variant_waves<double>(int);
+template int solve_variant_shape<float>(int, int *, int *);
+template int solve_variant_shape<double>(int, int *, int *);
 template hipError_t launch_solve<float>(const SolveParams<float> &, int, int64_t, hipStream_t);
 template hipError_t launch_solve<double>(const SolveParams<double> &, int, int64_t, hipStream_t);
 

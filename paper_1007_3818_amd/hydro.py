@@ -168,7 +168,13 @@ def pack_periodic(state, gx, gy, gz, out=None):
 
 
 def solver_variants(dtype) -> list:
-    """Waves-per-SIMD targets of the compiled solver variants for a dtype."""
+    """(threads per work-group, waves per SIMD) of the compiled solver variants."""
     f32 = int(_f32(dtype))
     L = _native.lib()
-    return [L.gamer_solver_variant_waves(f32, v) for v in range(L.gamer_solver_variants(f32))]
+    out = []
+    for v in range(L.gamer_solver_variants(f32)):
+        th, wv = ctypes.c_int(0), ctypes.c_int(0)
+        _native.check(L.gamer_solver_variant_shape(f32, v, ctypes.cast(ctypes.byref(th), ctypes.c_void_p),
+                                                   ctypes.cast(ctypes.byref(wv), ctypes.c_void_p)))
+        out.append((th.value, wv.value))
+    return out

@@ -43,12 +43,17 @@ def test_opts_struct_layout():
 
 
 def test_solver_variants(lib):
+    th, wv = ctypes.c_int(0), ctypes.c_int(0)
+    pth = ctypes.cast(ctypes.byref(th), ctypes.c_void_p)
+    pwv = ctypes.cast(ctypes.byref(wv), ctypes.c_void_p)
     for f32 in (0, 1):
         n = lib.gamer_solver_variants(f32)
         assert n >= 1
-        waves = [lib.gamer_solver_variant_waves(f32, v) for v in range(n)]
-        assert all(1 <= w <= 8 for w in waves)
-        assert lib.gamer_solver_variant_waves(f32, n) == 0
+        for v in range(n):
+            assert lib.gamer_solver_variant_shape(f32, v, pth, pwv) == 0
+            assert th.value in (256, 320) and 1 <= wv.value <= 8
+        assert lib.gamer_solver_variant_shape(f32, n, pth, pwv) == _native.GAMER_EINVAL
+        assert lib.gamer_solver_variant_shape(f32, 0, None, pwv) == _native.GAMER_EINVAL
 
 
 def test_version(lib):
