@@ -74,7 +74,11 @@ def read_traffic(kernel_tag: str, variant: int, grid: int, n_groups: int):
     return float(v) if v else None
 
 
-def bench_dtype(tag, state, g, dh, steps, warmup):
+def progress(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def bench_dtype(tag, state, g, dh, steps, warmup, shape=None):
     import torch
     from paper_1007_3818_amd import autotune, hydro
 
@@ -92,8 +96,14 @@ def bench_dtype(tag, state, g, dh, steps, warmup):
     hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev, totals_out=totals)
 
     # pick the solver variant and launch grid for this batch on this device
-    tuned = autotune.tune(padded, dt_dev, dh_dev, GAMMA, use_cache=False)
-    variant, grid = tuned["variant"], tuned["grid"]
+    if shape is None:
+        progress(f"{tag}: tuning launch shape")
+        tuned = autotune.tune(padded, dt_dev, dh_dev, GAMMA, use_cache=False)
+        variant, grid = tuned["variant"], tuned["grid"]
+    else:
+        variant, grid = shape
+        tuned = {"table": []}
+    progress(f"{tag}: timing variant {variant} grid {grid}")
 
     def step(ev=None):
         if ev is not None:
@@ -142,6 +152,7 @@ def bench_dtype(tag, state, g, dh, steps, warmup):
     tot = totals.cpu().tolist()
     dt_used = float(dt_dev.item())
 
+    progress(f"{tag}: timing the step with ghost fill")
     # the same step preceded by the periodic ghost fill of an evolving grid
     cur, nxt = out, torch.empty_like(out)  # `out` holds a valid state after the timed steps
     for _ in range(warmup):
@@ -215,6 +226,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for counter scaling)")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="use this compiled solver variant (with --grid) instead of tuning")
+    ap.add_argument("--grid", type=int, default=0, help="launch grid with --variant (0: one per group)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
@@ -225,6 +239,7 @@ def main():
     from paper_1007_3818_amd import hydro, workloads
 
     dev = torch.device("cuda:0")
+    progress("start")
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         b = torch.empty_like(a)
@@ -236,11 +251,13 @@ def main():
     g = n // 16
     state, dh = workloads.smooth_modes(n=n, kmax=kmax, workload=args.workload, device=dev)
     n_groups = g ** 3
+    progress(f"workload {args.workload} generated ({n_groups} groups)")
+    shape = None if args.variant is None else (args.variant, args.grid)
     res = {}
     if args.dtype in ("f32", "both"):
-        res["f32"] = bench_dtype("f32", state.float(), g, dh, args.steps, args.warmup)
+        res["f32"] = bench_dtype("f32", state.float(), g, dh, args.steps, args.warmup, shape)
     if args.dtype in ("f64", "both"):
-        res["f64"] = bench_dtype("f64", state, g, dh, args.steps, args.warmup)
+        res["f64"] = bench_dtype("f64", state, g, dh, args.steps, args.warmup, shape)
     main_tag = "f32" if "f32" in res else "f64"
     m = res[main_tag]
     line = {
@@ -275,6 +292,7 @@ def main():
             host_pad = oracle.pack_periodic(state.cpu().numpy(), g, g, g)
         else:  # a bounded sample of the large workload: its first 512 groups
             host_pad = oracle.pack_periodic_subset(state, g, g, g, range(512))
+        progress("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(host_pad, dh, dt)
     print(json.dumps(line), flush=True)
 
