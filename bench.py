@@ -152,26 +152,46 @@ def bench_dtype(tag, state, g, dh, steps, warmup, shape=None):
     tot = totals.cpu().tolist()
     dt_used = float(dt_dev.item())
 
-    progress(f"{tag}: timing the step with ghost fill")
-    # the same step preceded by the periodic ghost fill of an evolving grid
-    cur, nxt = out, torch.empty_like(out)  # `out` holds a valid state after the timed steps
-    for _ in range(warmup):
+    def timed_loop(one_step):
+        # `out` holds a valid state after the timed steps; evolve it from there
+        cur, nxt = out, torch.empty_like(out)
+        for _ in range(warmup):
+            one_step(cur, nxt)
+            cur, nxt = nxt, cur
+        torch.cuda.synchronize()
+        t0.record()
+        for _ in range(steps):
+            one_step(cur, nxt)
+            cur, nxt = nxt, cur
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / steps
+
+    # the periodic grid advanced by the fused step (ghost cells read in place)
+    if shape is None:
+        progress(f"{tag}: tuning the fused periodic step")
+        ftuned = autotune.tune(out, dt_dev, dh_dev, GAMMA, use_cache=False, periodic=(g, g, g))
+        fvariant, fgrid = ftuned["variant"], ftuned["grid"]
+    else:
+        fvariant, fgrid = shape
+    progress(f"{tag}: timing the fused periodic step, variant {fvariant} grid {fgrid}")
+
+    def fused_step(cur, nxt):
+        hydro.hydro_solve_periodic(cur, g, g, g, dt_dev, dh_dev, GAMMA, out=nxt, group_stats=stats,
+                                   variant=fvariant, grid=fgrid)
+        hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev, totals_out=totals)
+
+    ms_fused = timed_loop(fused_step)
+
+    progress(f"{tag}: timing ghost-fill kernel + batched step")
+
+    def packed_step(cur, nxt):
         hydro.pack_periodic(cur, g, g, g, out=padded)
         hydro.hydro_solve_batched(padded, None, dt_dev, dh_dev, GAMMA, out=nxt, group_stats=stats,
                                   variant=variant, grid=grid)
         hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev, totals_out=totals)
-        cur, nxt = nxt, cur
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(steps):
-        hydro.pack_periodic(cur, g, g, g, out=padded)
-        hydro.hydro_solve_batched(padded, None, dt_dev, dh_dev, GAMMA, out=nxt, group_stats=stats,
-                                  variant=variant, grid=grid)
-        hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev, totals_out=totals)
-        cur, nxt = nxt, cur
-    t1.record()
-    torch.cuda.synchronize()
-    ms_full = t0.elapsed_time(t1) / steps
+
+    ms_full = timed_loop(packed_step)
     return {
         "value": cells / (ms_step * 1e-3),
         "ms_per_step": ms_step,
@@ -183,9 +203,77 @@ def bench_dtype(tag, state, g, dh, steps, warmup, shape=None):
         "tuning": {"variant": variant, "threads": hydro.solver_variants(padded.dtype)[variant][0],
                    "waves_per_simd": hydro.solver_variants(padded.dtype)[variant][1],
                    "grid": grid, "candidates": tuned["table"]},
+        "periodic_fused": {"ms_per_step": ms_fused, "cell_updates_per_s": cells / (ms_fused * 1e-3),
+                           "variant": fvariant, "grid": fgrid,
+                           "step": "solve reading ghost cells from neighbouring groups + reduce, "
+                                   "grid evolving"},
         "with_ghost_fill": {"ms_per_step": ms_full, "cell_updates_per_s": cells / (ms_full * 1e-3),
                             "step": "periodic ghost fill + batched solve + reduce, grid evolving"},
     }
+
+
+def bench_amr(tag, state, g, dh, steps):
+    """The coarse/fine kernels on a refined sphere of the same grid: patches
+    whose centre lies within 0.3 of the box size from the centre become fine
+    groups.  Per kernel: mean time over `steps` calls, algorithmic bytes, and
+    the fraction of the HBM peak.  Values of the fine level do not change the
+    work these kernels do, so the fine groups hold the injected coarse state and
+    the fine fluxes are copies of coarse ones."""
+    import numpy as np
+    import torch
+    from paper_1007_3818_amd import amr, hydro
+
+    dev = state.device
+    npch = 2 * g
+    c = (np.arange(npch) + 0.5) / npch - 0.5
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    sel = np.argwhere(X ** 2 + Y ** 2 + Z ** 2 < 0.3 ** 2)  # (pz, py, px)
+    patches = [((px // 2) + g * ((py // 2) + g * (pz // 2)), (px % 2) + 2 * (py % 2) + 4 * (pz % 2))
+               for pz, py, px in sel]
+    parent, faces = amr.refine(g, g, g, patches)
+    nf, nr = len(parent), len(faces)
+    elem = state.element_size()
+    parent_t = torch.from_numpy(parent).to(dev)
+    faces_t = amr.faces_to_device(faces, dev)
+    coarse = state.clone()
+    cfl = torch.empty((g ** 3, 3, 3, 5, 16, 16), dtype=state.dtype, device=dev)
+    dt_dev = torch.full((1,), 1e-4, dtype=torch.float64, device=dev)
+    dh_dev = torch.full((1,), dh, dtype=torch.float64, device=dev)
+    hydro.hydro_solve_batched(hydro.pack_periodic(state, g, g, g), None, dt_dev, dh_dev, GAMMA,
+                              fluxes_out=cfl)
+    fine = coarse[torch.as_tensor(parent // 8, device=dev)].contiguous()
+    ffl = cfl[torch.as_tensor(parent // 8, device=dev)].contiguous()
+    acc = torch.zeros((nf, 3, 3, 5, 16, 16), dtype=torch.float64, device=dev)
+    bad = torch.zeros(1, dtype=torch.int32, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(steps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / steps
+
+    flux_vals = 3 * 3 * 5 * 16 * 16
+    rows = {
+        "flux_accumulate": (timed(lambda: hydro.flux_accumulate(ffl, dt_dev, acc=acc)),
+                            nf * flux_vals * (elem + 16)),
+        "flux_correct (3 launches)": (timed(lambda: hydro.flux_correct(coarse, cfl, acc, faces_t, dt_dev,
+                                                                         dh_dev, n_bad=bad)),
+                                      nr * 320 * (3 * elem + 32)),
+        "restrict": (timed(lambda: hydro.restrict(fine, parent_t, coarse, n_bad=bad)),
+                     nf * 5 * elem * (16 ** 3 + 8 ** 3)),
+    }
+    if int(bad.item()) != 0:
+        raise RuntimeError("AMR kernels reported bad records")
+    out = {"fine_groups": nf, "cf_face_records": nr}
+    for k, (ms, b) in rows.items():
+        out[k] = {"us": ms * 1e3, "algorithmic_bytes": b, "GBps": b / (ms * 1e-3) / 1e9,
+                  "hbm_frac": b / (ms * 1e-3) / HBM_PEAK}
+    return out
 
 
 def cpu_baseline(padded64_host, dh, dt):
@@ -224,6 +312,7 @@ def main():
     ap.add_argument("--workload", type=int, choices=[2, 5], default=2,
                     help="2: smooth modes 256^3 (the metric's configuration); 5: 1024^3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-amr", action="store_true", help="skip the coarse/fine kernel timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--variant", type=int, default=None,
@@ -258,6 +347,11 @@ def main():
         res["f32"] = bench_dtype("f32", state.float(), g, dh, args.steps, args.warmup, shape)
     if args.dtype in ("f64", "both"):
         res["f64"] = bench_dtype("f64", state, g, dh, args.steps, args.warmup, shape)
+    if not args.no_amr:
+        for tag in list(res):
+            progress(f"{tag}: coarse/fine correction and restriction kernels")
+            st = state.float() if tag == "f32" else state
+            res[tag]["amr"] = bench_amr(tag, st, g, dh, max(args.steps, 10))
     main_tag = "f32" if "f32" in res else "f64"
     m = res[main_tag]
     line = {

@@ -69,8 +69,10 @@ typedef struct gamer_opts {
     double theta;
     /* Compiled solver variant, 0 .. gamer_solver_variants(f32)-1 (0 is the
      * default).  Variants differ in work-group size and in the register budget
-     * they were built for (waves per SIMD); their results are bitwise
-     * identical. */
+     * they were built for (waves per SIMD).  Each is deterministic, and its
+     * launch grids give bitwise equal results; across variants FP64 results
+     * agree to about 1e-13 and FP32 results to about 1e-6 relative (the
+     * compiler may contract multiply-adds differently). */
     int32_t variant;
     /* Work-groups launched: 0 launches one per group; g > 0 launches
      * min(g, n_groups) persistent work-groups that stride over the groups. */
@@ -129,6 +131,27 @@ int gamer_hydro_solve_batched_f32(const float *groups_in, int64_t n_groups, cons
                                   double gamma, float *fluxes_out, float *groups_out,
                                   double *group_stats, const gamer_opts *opts);
 
+/* ---- one step of a uniform periodic grid, ghost cells fetched in place ---
+ * The same step as gamer_hydro_solve_batched, for the interior state of a
+ * uniform periodic grid of gx x gy x gz groups ([gx*gy*gz][5][16][16][16],
+ * group index x + gx (y + gy z)): each group's two ghost layers are read from
+ * its periodic neighbours while it is advanced, so no padded copy is built.
+ * (The paper's Sec. 2 notes that preparing ghost zones costs more than the GPU
+ * solver itself; for this uniform case the preparation disappears.)  Results
+ * equal those of gamer_pack_periodic followed by the batched step with the
+ * same variant: bitwise in FP64, to rounding in FP32 (the two are separate
+ * compilations, and float multiply-adds may contract differently).  dt_dev, dh_dev: device double [1].  state_out must not be
+ * state.  group_stats, fluxes_out, opts as in the batched step.
+ * Errors: GAMER_EINVAL for gx, gy, gz outside [1, 2^24] or gx*gy*gz >= 2^31,
+ * NULL state / state_out / dt_dev / dh_dev, state_out == state, gamma or opts
+ * as in the batched step. */
+int gamer_hydro_solve_periodic(const double *state, int gx, int gy, int gz, const double *dt_dev,
+                               const double *dh_dev, double gamma, double *fluxes_out,
+                               double *state_out, double *group_stats, const gamer_opts *opts);
+int gamer_hydro_solve_periodic_f32(const float *state, int gx, int gy, int gz, const double *dt_dev,
+                                   const double *dh_dev, double gamma, float *fluxes_out,
+                                   float *state_out, double *group_stats, const gamer_opts *opts);
+
 /* ---- reduction of group stats to time steps and totals -----------------
  * From group_stats [n_groups][8] (as written by the batched step or by
  * gamer_group_stats), computes on the device, in a fixed order (results are
@@ -181,6 +204,83 @@ int gamer_conserved_sums_f32(const float *groups, int64_t n_groups, double dh,
  * gx*gy*gz*100 > INT32_MAX (about 21 million groups), NULL or misaligned arrays. */
 int gamer_pack_periodic(const double *state, int gx, int gy, int gz, double *padded);
 int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *padded);
+
+/* ---- two refinement levels: flux correction and restriction -------------
+ * The steps that follow the solver when a coarse level and a fine level at
+ * half the spacing are advanced together, as in GAMER's patch-based AMR
+ * (Schive et al. 2010, the code the paper extends, Sec. 1): a coarse group is
+ * 2x2x2 patches of 8^3 cells; refining a patch gives one fine group of 16^3
+ * cells.  After one coarse step and the fine level's sub-steps:
+ *   - flux correction (conservative refluxing, Berger & Colella 1989): an
+ *     unrefined coarse cell next to a coarse/fine face was updated with the
+ *     coarse flux F_C through that face; it is corrected to use instead the
+ *     fine fluxes through the same face, summed over the fine sub-steps s with
+ *     their dt_s and averaged over the 2x2 fine faces that tile the coarse face:
+ *       Phi = sum_s dt_s (1/4) sum_faces F_f,s,   delta = (dt_C F_C - Phi) / dh_C,
+ *     the cell below the face (lower index along d) gains delta, the cell
+ *     above it loses delta;
+ *   - restriction: each coarse cell covered by a fine group takes the mean of
+ *     its 2x2x2 fine children.
+ * Together they keep the composite (coarse + fine) totals conserved. */
+
+/* One coarse/fine face: an 8x8 patch face of coarse cells next to a fine group.
+ * 24 bytes, 8-byte aligned. */
+typedef struct gamer_cf_face {
+    int64_t coarse_group; /* group holding the unrefined coarse cells */
+    int64_t fine_group;   /* fine group on the other side of the face */
+    int8_t dir;           /* face normal: 0 x, 1 y, 2 z */
+    int8_t coarse_face;   /* 0, 1, 2: the face at index 0, 8 or 16 of the coarse
+                             group along dir (the coarse flux-plane index) */
+    int8_t side;          /* 0: the coarse cells lie below the face (index
+                             8*coarse_face - 1) and the fine group's face 0 is
+                             the face; 1: above (index 8*coarse_face), the fine
+                             group's face 16 */
+    int8_t qs, qf;        /* 0/1: which 8x8 quarter of the 16x16 coarse plane,
+                             along the plane's slow and fast transverse axes */
+    int8_t reserved[3];
+} gamer_cf_face;
+
+/* acc (double, the flux-plane layout [n_groups][3][3][5][16][16]) =
+ * (reset ? 0 : acc) + dt_dev[0] * fluxes, element by element.  Summing a fine
+ * level's fluxes_out over its sub-steps gives the Phi above (before the 1/4
+ * area average).  acc must be 16-byte aligned.
+ * Errors: GAMER_EINVAL for n_groups < 0, NULL or misaligned arrays. */
+int gamer_flux_accumulate(const double *fluxes, int64_t n_groups, const double *dt_dev, int reset,
+                          double *acc);
+int gamer_flux_accumulate_f32(const float *fluxes, int64_t n_groups, const double *dt_dev,
+                              int reset, double *acc);
+
+/* Applies every face record's correction to the coarse interior groups
+ * coarse [n_coarse][5][16][16][16] in place, with coarse_fluxes the coarse
+ * step's fluxes_out, fine_acc [n_fine][3][3][5][16][16] the fine level's
+ * accumulated fluxes (gamer_flux_accumulate), dt_dev / dh_dev the coarse
+ * level's dt and dh (device double [1]), faces [n_faces] in device memory.
+ * The x records are applied first, then y, then z (three launches); records
+ * of one direction must name distinct coarse cells.  A record with an index
+ * or field out of range is skipped and, when n_bad_dev (device int32) is not
+ * NULL, counted there (the caller zeroes it).  The FP32 variant forms each
+ * corrected value in double and rounds once per record.
+ * Errors: GAMER_EINVAL for negative counts, NULL arrays, misaligned faces. */
+int gamer_flux_correct(double *coarse, int64_t n_coarse, const double *coarse_fluxes,
+                       const double *fine_acc, int64_t n_fine, const gamer_cf_face *faces,
+                       int64_t n_faces, const double *dt_dev, const double *dh_dev,
+                       int32_t *n_bad_dev);
+int gamer_flux_correct_f32(float *coarse, int64_t n_coarse, const float *coarse_fluxes,
+                           const double *fine_acc, int64_t n_fine, const gamer_cf_face *faces,
+                           int64_t n_faces, const double *dt_dev, const double *dh_dev,
+                           int32_t *n_bad_dev);
+
+/* Restriction: for each fine group f [n_fine][5][16][16][16] with
+ * parent[f] = coarse_group * 8 + octant (octant = ox + 2 oy + 4 oz: the
+ * coarse group's patch it covers), the 8^3 coarse cells of that patch take the
+ * mean of their 2x2x2 children, summed in double and rounded once.  parent[f]
+ * < 0 skips the group; a parent beyond the coarse array is skipped and counted
+ * in n_bad_dev as above.  parent is device memory.
+ * Errors: GAMER_EINVAL for negative counts, n_fine above 2^27, NULL arrays. */
+int gamer_restrict(const double *fine, const int64_t *parent, int64_t n_fine, double *coarse,
+                   int64_t n_coarse, int32_t *n_bad_dev);
+int gamer_restrict_f32(const float *fine, const int64_t *parent, int64_t n_fine, float *coarse,
+                       int64_t n_coarse, int32_t *n_bad_dev);
 
 #ifdef __cplusplus
 }

@@ -40,6 +40,8 @@ SIGNATURES = {
     "gamer_hydro_solve_f32": (_I, [_P, _I64, _D, _D, _D, _P, _P]),
     "gamer_hydro_solve_batched": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO]),
     "gamer_hydro_solve_batched_f32": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO]),
+    "gamer_hydro_solve_periodic": (_I, [_P, _I, _I, _I, _P, _P, _D, _P, _P, _P, _PO]),
+    "gamer_hydro_solve_periodic_f32": (_I, [_P, _I, _I, _I, _P, _P, _D, _P, _P, _P, _PO]),
     "gamer_step_reduce": (_I, [_P, _I64, _P, _P, _I, _D, _P, _P]),
     "gamer_group_stats": (_I, [_P, _I64, _D, _P]),
     "gamer_group_stats_f32": (_I, [_P, _I64, _D, _P]),
@@ -49,6 +51,12 @@ SIGNATURES = {
     "gamer_conserved_sums_f32": (_I, [_P, _I64, _D, _P, _I]),
     "gamer_pack_periodic": (_I, [_P, _I, _I, _I, _P]),
     "gamer_pack_periodic_f32": (_I, [_P, _I, _I, _I, _P]),
+    "gamer_flux_accumulate": (_I, [_P, _I64, _P, _I, _P]),
+    "gamer_flux_accumulate_f32": (_I, [_P, _I64, _P, _I, _P]),
+    "gamer_flux_correct": (_I, [_P, _I64, _P, _P, _I64, _P, _I64, _P, _P, _P]),
+    "gamer_flux_correct_f32": (_I, [_P, _I64, _P, _P, _I64, _P, _I64, _P, _P, _P]),
+    "gamer_restrict": (_I, [_P, _P, _I64, _P, _I64, _P]),
+    "gamer_restrict_f32": (_I, [_P, _P, _I64, _P, _I64, _P]),
 }
 
 _lib = None

@@ -90,3 +90,12 @@ def covered_mask(gx: int, gy: int, gz: int, parent) -> np.ndarray:
         ox, oy, oz = o & 1, (o >> 1) & 1, (o >> 2) & 1
         m[g, 8 * oz:8 * oz + 8, 8 * oy:8 * oy + 8, 8 * ox:8 * ox + 8] = True
     return m
+
+
+def faces_to_device(faces: np.ndarray, device) -> "torch.Tensor":
+    """Face records as the (n, 24) uint8 GPU tensor the flux-correction entry
+    point takes (the bytes of the gamer_cf_face array)."""
+    import torch
+    faces = np.ascontiguousarray(faces, dtype=CF_FACE_DTYPE)
+    raw = faces.view(np.uint8).reshape(-1, CF_FACE_DTYPE.itemsize)
+    return torch.from_numpy(raw.copy()).to(device)

@@ -25,10 +25,11 @@ def cache_path() -> str:
         os.path.expanduser("~"), ".cache", "gamer_hydro", "tune.json")
 
 
-def _key(dtype, n_groups: int) -> str:
+def _key(dtype, n_groups: int, periodic: bool = False) -> str:
     name = torch.cuda.get_device_name(0)
     bucket = 1 << max(0, (int(n_groups) - 1).bit_length())
-    return f"{name}|{'f32' if dtype == torch.float32 else 'f64'}|{bucket}"
+    kind = "|periodic" if periodic else ""
+    return f"{name}|{'f32' if dtype == torch.float32 else 'f64'}|{bucket}{kind}"
 
 
 def candidates(dtype, n_groups: int):
@@ -70,19 +71,29 @@ def max_rel_diff(a: torch.Tensor, b: torch.Tensor) -> float:
 
 
 def tune(padded: torch.Tensor, dt_dev: torch.Tensor, dh_dev: torch.Tensor, gamma: float,
-         level=None, reps: int = 5, use_cache: bool = True) -> dict:
-    """Return {"variant", "grid", "ms", "table"} for this batch."""
-    key = _key(padded.dtype, padded.shape[0])
+         level=None, reps: int = 5, use_cache: bool = True, periodic=None) -> dict:
+    """Return {"variant", "grid", "ms", "table"} for this batch.  With
+    ``periodic=(gx, gy, gz)``, ``padded`` is instead the interior state of a
+    periodic grid and the fused periodic step is tuned."""
+    key = _key(padded.dtype, padded.shape[0], periodic is not None)
     if use_cache:
         hit = _load().get(key)
         if hit is not None:
             return dict(hit, cached=True)
     n = padded.shape[0]
     out = torch.empty((n, 5, 16, 16, 16), dtype=padded.dtype, device=padded.device)
+
+    def run(v, g):
+        if periodic is None:
+            hydro.hydro_solve_batched(padded, level, dt_dev, dh_dev, gamma, out=out, variant=v, grid=g)
+        else:
+            hydro.hydro_solve_periodic(padded, *periodic, dt_dev, dh_dev, gamma, out=out, variant=v,
+                                       grid=g)
+
     ref = None
     table = []
     for v, g in candidates(padded.dtype, n):
-        hydro.hydro_solve_batched(padded, level, dt_dev, dh_dev, gamma, out=out, variant=v, grid=g)
+        run(v, g)
         torch.cuda.synchronize()
         if ref is None:
             ref = out.clone()
@@ -94,7 +105,7 @@ def tune(padded: torch.Tensor, dt_dev: torch.Tensor, dh_dev: torch.Tensor, gamma
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
         ev[0].record()
         for _ in range(reps):
-            hydro.hydro_solve_batched(padded, level, dt_dev, dh_dev, gamma, out=out, variant=v, grid=g)
+            run(v, g)
         ev[1].record()
         torch.cuda.synchronize()
         th, wv = hydro.solver_variants(padded.dtype)[v]

@@ -87,6 +87,7 @@ int solve_common(const T *in, int64_t n, const int8_t *level, const double *dt_d
         return fail(GAMER_EINVAL, "n_levels must lie in [1, %d]", GAMER_MAX_LEVELS);
     SolveParams<T> p;
     p.in = in;
+    p.gx = p.gy = p.gz = 0;
     p.out = out;
     p.flux = fluxes;
     p.stats = stats;
@@ -95,6 +96,45 @@ int solve_common(const T *in, int64_t n, const int8_t *level, const double *dt_d
     p.dh_dev = dh_dev;
     p.dt = dt;
     p.dh = dh;
+    p.gamma = gamma;
+    p.theta = theta;
+    p.n_groups = n;
+    return check_hip(launch_solve<T>(p, variant, grid, g_stream), "solver launch");
+}
+
+template <typename T>
+int periodic_common(const T *state, int gx, int gy, int gz, const double *dt_dev,
+                    const double *dh_dev, double gamma, T *fluxes, T *out, double *stats,
+                    const gamer_opts *opts) {
+    g_err[0] = 0;
+    if (gx < 1 || gy < 1 || gz < 1) return fail(GAMER_EINVAL, "gx, gy, gz must be >= 1");
+    const int64_t n = int64_t(gx) * gy * gz;
+    if (int64_t(gx) * NI > (1 << 28) || int64_t(gy) * NI > (1 << 28) || int64_t(gz) * NI > (1 << 28) ||
+        n > INT32_MAX)
+        return fail(GAMER_EINVAL, "grid too large: gx, gy, gz <= 2^24 and gx*gy*gz < 2^31 required");
+    if (!state || !out || !dt_dev || !dh_dev) return fail(GAMER_EINVAL, "NULL array argument");
+    if (static_cast<const void *>(state) == static_cast<const void *>(out))
+        return fail(GAMER_EINVAL, "state and state_out must be different arrays");
+    if (!(isfinite(gamma) && gamma > 1.0)) return fail(GAMER_EINVAL, "gamma must be > 1");
+    const double theta = (opts && opts->theta != 0.0) ? opts->theta : 1.5;
+    if (!(theta >= 1.0 && theta <= 2.0)) return fail(GAMER_EINVAL, "theta must lie in [1, 2]");
+    const int variant = opts ? opts->variant : 0;
+    const int64_t grid = opts ? opts->grid : 0;
+    if (variant < 0 || variant >= solve_variant_count<T>())
+        return fail(GAMER_EINVAL, "variant must lie in [0, %d)", solve_variant_count<T>());
+    if (grid < 0) return fail(GAMER_EINVAL, "grid must be >= 0");
+    SolveParams<T> p;
+    p.in = state;
+    p.gx = gx;
+    p.gy = gy;
+    p.gz = gz;
+    p.out = out;
+    p.flux = fluxes;
+    p.stats = stats;
+    p.level = nullptr;
+    p.dt_dev = dt_dev;
+    p.dh_dev = dh_dev;
+    p.dt = p.dh = 0.0;
     p.gamma = gamma;
     p.theta = theta;
     p.n_groups = n;
@@ -183,6 +223,45 @@ int stats_common(const T *groups, int64_t n, double gamma, double *stats) {
     return check_hip(launch_group_stats<T>(groups, n, gamma, stats, g_stream), "stats launch");
 }
 
+template <typename T>
+int accumulate_common(const T *fluxes, int64_t n, const double *dt_dev, int reset, double *acc) {
+    g_err[0] = 0;
+    if (n < 0) return fail(GAMER_EINVAL, "n_groups < 0");
+    if (n == 0) return GAMER_OK;
+    if (!fluxes || !dt_dev || !acc) return fail(GAMER_EINVAL, "NULL array argument");
+    if (reinterpret_cast<uintptr_t>(acc) % 16) return fail(GAMER_EINVAL, "acc must be 16-byte aligned");
+    return check_hip(launch_flux_accumulate<T>(fluxes, n, dt_dev, reset, acc, g_stream),
+                     "flux accumulate launch");
+}
+
+template <typename T>
+int correct_common(T *coarse, int64_t n_coarse, const T *coarse_fluxes, const double *fine_acc,
+                   int64_t n_fine, const gamer_cf_face *faces, int64_t n_faces, const double *dt_dev,
+                   const double *dh_dev, int32_t *n_bad) {
+    g_err[0] = 0;
+    if (n_coarse < 0 || n_fine < 0 || n_faces < 0) return fail(GAMER_EINVAL, "negative count");
+    if (n_faces > (int64_t(1) << 32)) return fail(GAMER_EINVAL, "n_faces above 2^32");
+    if (n_faces == 0) return GAMER_OK;
+    if (!coarse || !coarse_fluxes || !fine_acc || !faces || !dt_dev || !dh_dev)
+        return fail(GAMER_EINVAL, "NULL array argument");
+    if (reinterpret_cast<uintptr_t>(faces) % 8) return fail(GAMER_EINVAL, "faces must be 8-byte aligned");
+    return check_hip(launch_flux_correct<T>(coarse, n_coarse, coarse_fluxes, fine_acc, n_fine, faces,
+                                            n_faces, dt_dev, dh_dev, n_bad, g_stream),
+                     "flux correct launch");
+}
+
+template <typename T>
+int restrict_common(const T *fine, const int64_t *parent, int64_t n_fine, T *coarse, int64_t n_coarse,
+                    int32_t *n_bad) {
+    g_err[0] = 0;
+    if (n_fine < 0 || n_coarse < 0) return fail(GAMER_EINVAL, "negative count");
+    if (n_fine > (int64_t(1) << 27)) return fail(GAMER_EINVAL, "n_fine above 2^27");
+    if (n_fine == 0) return GAMER_OK;
+    if (!fine || !parent || !coarse) return fail(GAMER_EINVAL, "NULL array argument");
+    return check_hip(launch_restrict<T>(fine, parent, n_fine, coarse, n_coarse, n_bad, g_stream),
+                     "restrict launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -240,6 +319,20 @@ int gamer_hydro_solve_batched_f32(const float *groups_in, int64_t n_groups, cons
                                gamma, fluxes_out, groups_out, group_stats, opts);
 }
 
+int gamer_hydro_solve_periodic(const double *state, int gx, int gy, int gz, const double *dt_dev,
+                               const double *dh_dev, double gamma, double *fluxes_out,
+                               double *state_out, double *group_stats, const gamer_opts *opts) {
+    return periodic_common<double>(state, gx, gy, gz, dt_dev, dh_dev, gamma, fluxes_out, state_out,
+                                   group_stats, opts);
+}
+
+int gamer_hydro_solve_periodic_f32(const float *state, int gx, int gy, int gz, const double *dt_dev,
+                                   const double *dh_dev, double gamma, float *fluxes_out,
+                                   float *state_out, double *group_stats, const gamer_opts *opts) {
+    return periodic_common<float>(state, gx, gy, gz, dt_dev, dh_dev, gamma, fluxes_out, state_out,
+                                  group_stats, opts);
+}
+
 int gamer_step_reduce(const double *group_stats, int64_t n_groups, const int8_t *level,
                       const double *dh_dev, int n_levels, double cfl, double *dt_dev_out,
                       double *totals_dev_out) {
@@ -291,6 +384,42 @@ int gamer_pack_periodic(const double *state, int gx, int gy, int gz, double *pad
 
 int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *padded) {
     return pack_common<float>(state, gx, gy, gz, padded);
+}
+
+int gamer_flux_accumulate(const double *fluxes, int64_t n_groups, const double *dt_dev, int reset,
+                          double *acc) {
+    return accumulate_common<double>(fluxes, n_groups, dt_dev, reset, acc);
+}
+
+int gamer_flux_accumulate_f32(const float *fluxes, int64_t n_groups, const double *dt_dev,
+                              int reset, double *acc) {
+    return accumulate_common<float>(fluxes, n_groups, dt_dev, reset, acc);
+}
+
+int gamer_flux_correct(double *coarse, int64_t n_coarse, const double *coarse_fluxes,
+                       const double *fine_acc, int64_t n_fine, const gamer_cf_face *faces,
+                       int64_t n_faces, const double *dt_dev, const double *dh_dev,
+                       int32_t *n_bad_dev) {
+    return correct_common<double>(coarse, n_coarse, coarse_fluxes, fine_acc, n_fine, faces, n_faces,
+                                  dt_dev, dh_dev, n_bad_dev);
+}
+
+int gamer_flux_correct_f32(float *coarse, int64_t n_coarse, const float *coarse_fluxes,
+                           const double *fine_acc, int64_t n_fine, const gamer_cf_face *faces,
+                           int64_t n_faces, const double *dt_dev, const double *dh_dev,
+                           int32_t *n_bad_dev) {
+    return correct_common<float>(coarse, n_coarse, coarse_fluxes, fine_acc, n_fine, faces, n_faces,
+                                 dt_dev, dh_dev, n_bad_dev);
+}
+
+int gamer_restrict(const double *fine, const int64_t *parent, int64_t n_fine, double *coarse,
+                   int64_t n_coarse, int32_t *n_bad_dev) {
+    return restrict_common<double>(fine, parent, n_fine, coarse, n_coarse, n_bad_dev);
+}
+
+int gamer_restrict_f32(const float *fine, const int64_t *parent, int64_t n_fine, float *coarse,
+                       int64_t n_coarse, int32_t *n_bad_dev) {
+    return restrict_common<float>(fine, parent, n_fine, coarse, n_coarse, n_bad_dev);
 }
 
 }  // extern "C"

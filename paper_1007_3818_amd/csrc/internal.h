@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/gamer_hydro.h"
+
 namespace gamer {
 
 // Patch-group geometry: 16^3 interior cells, two ghost cells per side (the
@@ -22,7 +24,11 @@ constexpr int MAX_LEVELS = 32;
 
 template <typename T>
 struct SolveParams {
-    const T *in;          // [n][5][20][20][20]
+    // Input: padded groups [n][5][20][20][20] (gx == 0), or the interior state of
+    // a periodic grid of gx x gy x gz groups [n][5][16][16][16] whose ghost cells
+    // are read from the neighbouring groups (gx > 0).
+    const T *in;
+    int gx, gy, gz;
     T *out;               // [n][5][16][16][16]
     T *flux;              // [n][3][3][5][16][16] or nullptr
     double *stats;        // [n][8] or nullptr
@@ -54,5 +60,18 @@ hipError_t launch_group_stats(const T *groups, int64_t n, double gamma, double *
 hipError_t launch_reduce(const double *stats, int64_t n, const int8_t *level, const double *dh_dev,
                          double dh, int n_levels, double cfl, double *dt_out, double *totals_out,
                          hipStream_t s);
+
+// two refinement levels (amr.hip)
+template <typename T>
+hipError_t launch_flux_accumulate(const T *fluxes, int64_t n_groups, const double *dt_dev, int reset,
+                                  double *acc, hipStream_t s);
+template <typename T>
+hipError_t launch_flux_correct(T *coarse, int64_t n_coarse, const T *coarse_fluxes, const double *acc,
+                               int64_t n_fine, const gamer_cf_face *faces, int64_t n_faces,
+                               const double *dt_dev, const double *dh_dev, int32_t *n_bad,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_restrict(const T *fine, const int64_t *parent, int64_t n_fine, T *coarse,
+                           int64_t n_coarse, int32_t *n_bad, hipStream_t s);
 
 }  // namespace gamer

@@ -342,7 +342,7 @@ __device__ __forceinline__ void ring_cell(int r, int &ci, int &cj) {
 //  NT = 256: threads own the interior columns; in plane k the wave k mod 4 also
 //            computes the 64 ghost-layer cells in a second round (4 waves, one
 //            per SIMD).
-template <typename T, int NT, int WAVES>
+template <typename T, int NT, int WAVES, bool PERIODIC>
 __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT), amdgpu_waves_per_eu(WAVES, 8)))
 void solve_kernel(SolveParams<T> P) {
     static_assert(NT == 320 || NT == 256, "work-group shape");
@@ -365,18 +365,61 @@ void solve_kernel(SolveParams<T> P) {
             dh = P.dh_dev[lev];
         }
         const double dtdh = dt / dh;
-        const T *__restrict__ in = P.in + g * GIN;
+
+        // ---- where padded cell (ip, jp, kp) of this group lives in the input ----
+        // Padded input: the group's own padded block.  Periodic input: the cell at
+        // the wrapped global position, in whichever group holds it; an offset is
+        // (group index) * 20480 + (cell within the group), the group index split
+        // into an x/y part and a z part.
+        constexpr int VSTRIDE = PERIODIC ? NI * NI * NI : NP * NP * NP;
+        int bx = 0, by = 0, bz = 0;
+        if (PERIODIC) {
+            bx = int(g % P.gx);
+            by = int((g / P.gx) % P.gy);
+            bz = int(g / (int64_t(P.gx) * P.gy));
+        }
+        // x/y part: (group index part, cell part)
+        auto xy_part = [&](int ip, int jp, int &gpart) -> int {
+            if (!PERIODIC) {
+                gpart = 0;
+                return jp * NP + ip;
+            }
+            int X = bx * NI + ip - NG, Y = by * NI + jp - NG;
+            const int NX = P.gx * NI, NY = P.gy * NI;
+            X = X < 0 ? X + NX : (X >= NX ? X - NX : X);
+            Y = Y < 0 ? Y + NY : (Y >= NY ? Y - NY : Y);
+            gpart = X / NI + P.gx * (Y / NI);
+            return (Y % NI) * NI + (X % NI);
+        };
+        // z part, and the base pointer of a plane for the x/y group part 0
+        auto plane_base = [&](int kp) -> const T * {
+            if (!PERIODIC) return P.in + g * GIN + kp * NPL;
+            int Z = bz * NI + kp - NG;
+            const int NZ = P.gz * NI;
+            Z = Z < 0 ? Z + NZ : (Z >= NZ ? Z - NZ : Z);
+            return P.in + int64_t(P.gx) * P.gy * (Z / NI) * GOUT + (Z % NI) * (NI * NI);
+        };
+        auto cell_ptr = [&](int ip, int jp, int kp) -> const T * {
+            int gp;
+            const int cp = xy_part(ip, jp, gp);
+            return plane_base(kp) + int64_t(gp) * GOUT + cp;
+        };
 
         // ---- load helpers: positions t and t + NT of a padded plane ----
         const int p0 = t, p1 = t + NT;
         const bool has1 = p1 < NPL;
+        int gp0, gp1 = 0;
+        const int cp0 = xy_part(p0 % NP, p0 / NP, gp0);
+        const int cp1 = has1 ? xy_part(p1 % NP, p1 / NP, gp1) : cp0;
         T pre0[NV], pre1[NV];
         auto fetch = [&](int plane) {  // plane in -2..17
-            const T *src = in + (plane + NG) * NPL;
+            const T *src = plane_base(plane + NG);
+            const T *s0 = src + int64_t(gp0) * GOUT + cp0;
+            const T *s1 = src + int64_t(gp1) * GOUT + cp1;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                pre0[v] = src[v * NP * NPL + p0];
-                pre1[v] = has1 ? src[v * NP * NPL + p1] : T(1);
+                pre0[v] = s0[v * VSTRIDE];
+                pre1[v] = has1 ? s1[v * VSTRIDE] : T(1);
             }
         };
         auto store = [&](int plane) {  // prefetched conserved -> primitive LDS plane
@@ -464,7 +507,7 @@ void solve_kernel(SolveParams<T> P) {
                     ++n_pred;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        const T u0 = in[v * NP * NPL + (k + NG) * NPL + pos];
+                        const T u0 = cell_ptr(ci + NG, cj + NG, k + NG)[v * VSTRIDE];
 #pragma unroll
                         for (int d = 0; d < 3; ++d) Ub[d][0][v] = Ub[d][1][v] = u0;
                     }
@@ -589,12 +632,12 @@ void solve_kernel(SolveParams<T> P) {
                     // plane k-1 is complete: U - dt/dh ((dF_x + dF_y) + dF_z)
                     const int kk = k - 1;
                     T *dst = P.out + g * GOUT + kk * NINNER + t;
-                    const T *src = in + (kk + NG) * NPL + (jj + NG) * NP + (ii + NG);
+                    const T *src = cell_ptr(ii + NG, jj + NG, kk + NG);
                     T un[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         const double dfz = double(fzn[v]) - double(fz[v]);
-                        const double r = double(src[v * NP * NPL]) - dtdh * (S.dxy[v][t] + dfz);
+                        const double r = double(src[v * VSTRIDE]) - dtdh * (S.dxy[v][t] + dfz);
                         const T o = T(r);
                         dst[v * NI * NINNER] = o;
                         un[v] = o;
@@ -651,7 +694,12 @@ namespace {
 template <typename T, int V>
 void launch_variant(const SolveParams<T> &p, dim3 blocks, hipStream_t s) {
     constexpr Shape sh = Variants<T>::shape[V];
-    hipLaunchKernelGGL((solve_kernel<T, sh.threads, sh.waves>), blocks, dim3(sh.threads), 0, s, p);
+    if (p.gx > 0)
+        hipLaunchKernelGGL((solve_kernel<T, sh.threads, sh.waves, true>), blocks, dim3(sh.threads), 0,
+                           s, p);
+    else
+        hipLaunchKernelGGL((solve_kernel<T, sh.threads, sh.waves, false>), blocks, dim3(sh.threads), 0,
+                           s, p);
 }
 }  // namespace
 

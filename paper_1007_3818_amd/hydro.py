@@ -95,6 +95,37 @@ def hydro_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxe
     return out
 
 
+def hydro_solve_periodic(state, gx, gy, gz, dt_dev, dh_dev, gamma, out=None, fluxes_out=None,
+                         group_stats=None, theta=None, variant=None, grid=None):
+    """One step of a uniform periodic grid; ghost cells are read from the
+    neighbouring groups in place (no padded copy).  `out` must not be `state`."""
+    f32 = _f32(state.dtype)
+    _need(state, (NV, NI, NI, NI), state.dtype, "state")
+    n = state.shape[0]
+    if n != gx * gy * gz:
+        raise ValueError("state must hold gx*gy*gz groups")
+    if out is None:
+        out = torch.empty_like(state)
+    _need(out, (NV, NI, NI, NI), state.dtype, "out")
+    if fluxes_out is not None:
+        _need(fluxes_out, (3, 3, NV, NI, NI), state.dtype, "fluxes_out")
+    if group_stats is not None:
+        _need(group_stats, (8,), torch.float64, "group_stats")
+    for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
+        if t.dtype != torch.float64 or not t.is_cuda or t.numel() < 1:
+            raise ValueError(f"{nm} must be a GPU float64 tensor")
+    opts = None
+    if theta is not None or variant is not None or grid is not None:
+        opts = _native.GamerOpts(float(theta or 0.0), int(variant or 0), int(grid or 0))
+    _stream()
+    fn = (_native.lib().gamer_hydro_solve_periodic_f32 if f32
+          else _native.lib().gamer_hydro_solve_periodic)
+    _native.check(fn(_ptr(state), int(gx), int(gy), int(gz), _ptr(dt_dev), _ptr(dh_dev), float(gamma),
+                     _ptr(fluxes_out), _ptr(out), _ptr(group_stats),
+                     ctypes.byref(opts) if opts is not None else None))
+    return out
+
+
 def step_reduce(group_stats, level, dh_dev, cfl, dt_out=None, totals_out=None):
     """Per-level dt and conserved totals (+ fallback counts) from group stats, on the device."""
     _need(group_stats, (8,), torch.float64, "group_stats")
@@ -165,6 +196,72 @@ def pack_periodic(state, gx, gy, gz, out=None):
     fn = _native.lib().gamer_pack_periodic_f32 if f32 else _native.lib().gamer_pack_periodic
     _native.check(fn(_ptr(state), int(gx), int(gy), int(gz), _ptr(out)))
     return out
+
+
+# ---- two refinement levels ------------------------------------------------
+
+def _dev_scalar(t, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or t.numel() < 1:
+        raise ValueError(f"{name} must be a GPU float64 tensor")
+
+
+def _counter(n_bad):
+    if n_bad is None:
+        return None
+    if not isinstance(n_bad, torch.Tensor) or n_bad.dtype != torch.int32 or not n_bad.is_cuda:
+        raise ValueError("n_bad must be a GPU int32 tensor")
+    return _ptr(n_bad)
+
+
+def flux_accumulate(fluxes, dt_dev, acc=None, reset=False):
+    """acc = (reset or acc is None ? 0 : acc) + dt_dev[0] * fluxes, in float64."""
+    f32 = _f32(fluxes.dtype)
+    _need(fluxes, (3, 3, NV, NI, NI), fluxes.dtype, "fluxes")
+    _dev_scalar(dt_dev, "dt_dev")
+    if acc is None:
+        acc = torch.empty(fluxes.shape, dtype=torch.float64, device=fluxes.device)
+        reset = True
+    _need(acc, (3, 3, NV, NI, NI), torch.float64, "acc")
+    if acc.shape[0] != fluxes.shape[0]:
+        raise ValueError("acc and fluxes must hold the same number of groups")
+    _stream()
+    fn = _native.lib().gamer_flux_accumulate_f32 if f32 else _native.lib().gamer_flux_accumulate
+    _native.check(fn(_ptr(fluxes), fluxes.shape[0], _ptr(dt_dev), int(bool(reset)), _ptr(acc)))
+    return acc
+
+
+def flux_correct(coarse, coarse_fluxes, fine_acc, faces, dt_dev, dh_dev, n_bad=None):
+    """Coarse/fine flux correction of ``coarse`` in place.  ``faces``: a GPU
+    uint8 tensor (n, 24) of gamer_cf_face records (amr.faces_to_device)."""
+    f32 = _f32(coarse.dtype)
+    _need(coarse, (NV, NI, NI, NI), coarse.dtype, "coarse")
+    _need(coarse_fluxes, (3, 3, NV, NI, NI), coarse.dtype, "coarse_fluxes")
+    if coarse_fluxes.shape[0] != coarse.shape[0]:
+        raise ValueError("coarse_fluxes must hold one entry per coarse group")
+    _need(fine_acc, (3, 3, NV, NI, NI), torch.float64, "fine_acc")
+    _need(faces, (24,), torch.uint8, "faces")
+    _dev_scalar(dt_dev, "dt_dev")
+    _dev_scalar(dh_dev, "dh_dev")
+    _stream()
+    fn = _native.lib().gamer_flux_correct_f32 if f32 else _native.lib().gamer_flux_correct
+    _native.check(fn(_ptr(coarse), coarse.shape[0], _ptr(coarse_fluxes), _ptr(fine_acc), fine_acc.shape[0],
+                     _ptr(faces), faces.shape[0], _ptr(dt_dev), _ptr(dh_dev), _counter(n_bad)))
+    return coarse
+
+
+def restrict(fine, parent, coarse, n_bad=None):
+    """Restriction of fine groups onto ``coarse`` in place; parent: GPU int64
+    [n_fine] of coarse_group * 8 + octant."""
+    f32 = _f32(fine.dtype)
+    _need(fine, (NV, NI, NI, NI), fine.dtype, "fine")
+    _need(coarse, (NV, NI, NI, NI), fine.dtype, "coarse")
+    if not isinstance(parent, torch.Tensor) or parent.dtype != torch.int64 or not parent.is_cuda \
+            or parent.shape != (fine.shape[0],) or not parent.is_contiguous():
+        raise ValueError("parent must be a contiguous GPU int64 tensor with one entry per fine group")
+    _stream()
+    fn = _native.lib().gamer_restrict_f32 if f32 else _native.lib().gamer_restrict
+    _native.check(fn(_ptr(fine), _ptr(parent), fine.shape[0], _ptr(coarse), coarse.shape[0], _counter(n_bad)))
+    return coarse
 
 
 def solver_variants(dtype) -> list:

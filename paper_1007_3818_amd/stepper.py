@@ -3,10 +3,12 @@ refinement levels, with the time step kept on the device so that a step can be
 captured once in a HIP graph and replayed.
 
 One step of ``PeriodicGrid``:
-  1. ``gamer_pack_periodic``            state -> padded groups (ghost fill)
-  2. ``gamer_hydro_solve_batched``      padded -> new state, per-group stats,
-                                        dt read from ``dt_dev``
-  3. ``gamer_step_reduce``              stats -> next dt (CFL) and totals
+  1. ``gamer_hydro_solve_periodic``     state -> new state, per-group stats, the
+                                        ghost cells read from the neighbouring
+                                        groups, dt read from ``dt_dev``
+     (or, with ``fused=False``: ``gamer_pack_periodic`` into a padded copy, then
+     ``gamer_hydro_solve_batched``; bitwise the same in FP64, to rounding in FP32)
+  2. ``gamer_step_reduce``              stats -> next dt (CFL) and totals
 plus a device-side time accumulator.  Nothing synchronises with the host.
 """
 from __future__ import annotations
@@ -23,7 +25,7 @@ class PeriodicGrid:
 
     def __init__(self, state: torch.Tensor, gx: int, gy: int, gz: int, dh: float, gamma: float,
                  cfl: float = 0.5, theta: float | None = None, variant: int | None = None,
-                 grid: int | None = None):
+                 grid: int | None = None, fused: bool = True):
         if not state.is_cuda:
             raise ValueError("state must live on the GPU")
         self.gx, self.gy, self.gz = gx, gy, gz
@@ -33,7 +35,8 @@ class PeriodicGrid:
         dev, dt_ = state.device, state.dtype
         self.state = [state.contiguous().clone(), torch.empty_like(state)]
         self.cur = 0
-        self.padded = torch.empty((self.n, NV, NP, NP, NP), dtype=dt_, device=dev)
+        self.fused = fused
+        self.padded = None if fused else torch.empty((self.n, NV, NP, NP, NP), dtype=dt_, device=dev)
         self.stats = torch.empty((self.n, 8), dtype=torch.float64, device=dev)
         self.dh_dev = torch.full((1,), dh, dtype=torch.float64, device=dev)
         self.dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
@@ -50,10 +53,16 @@ class PeriodicGrid:
 
     def _step(self, src: int):
         dst = 1 - src
-        hydro.pack_periodic(self.state[src], self.gx, self.gy, self.gz, out=self.padded)
-        hydro.hydro_solve_batched(self.padded, None, self.dt_dev, self.dh_dev, self.gamma,
-                                  out=self.state[dst], group_stats=self.stats, theta=self.theta,
-                                  variant=self.variant, grid=self.grid)
+        if self.fused:
+            hydro.hydro_solve_periodic(self.state[src], self.gx, self.gy, self.gz, self.dt_dev,
+                                       self.dh_dev, self.gamma, out=self.state[dst],
+                                       group_stats=self.stats, theta=self.theta,
+                                       variant=self.variant, grid=self.grid)
+        else:
+            hydro.pack_periodic(self.state[src], self.gx, self.gy, self.gz, out=self.padded)
+            hydro.hydro_solve_batched(self.padded, None, self.dt_dev, self.dh_dev, self.gamma,
+                                      out=self.state[dst], group_stats=self.stats, theta=self.theta,
+                                      variant=self.variant, grid=self.grid)
         self.t_dev += self.dt_dev
         hydro.step_reduce(self.stats, None, self.dh_dev, self.cfl, dt_out=self.dt_dev,
                           totals_out=self.totals)

@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 19
+    assert len(names) == 27
     for n in names:
         assert hasattr(lib, n), n
         assert n in _native.SIGNATURES, n
@@ -100,6 +100,84 @@ def test_batched_argument_errors(lib):
     assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
     bad = _native.GamerOpts(1.5, 0, -4)
     assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+
+
+def test_periodic_argument_errors(lib):
+    Q = ctypes.c_void_p(0x2000)
+    for f in (lib.gamer_hydro_solve_periodic, lib.gamer_hydro_solve_periodic_f32):
+        assert f(P, 0, 1, 1, P, P, 1.4, None, Q, None, None) == _native.GAMER_EINVAL
+        assert f(P, 1, -2, 1, P, P, 1.4, None, Q, None, None) == _native.GAMER_EINVAL
+        assert f(P, 1 << 25, 1, 1, P, P, 1.4, None, Q, None, None) == _native.GAMER_EINVAL
+        assert f(P, 1 << 11, 1 << 11, 1 << 10, P, P, 1.4, None, Q, None, None) == _native.GAMER_EINVAL
+        assert b"too large" in lib.gamer_last_error()
+        assert f(None, 2, 2, 2, P, P, 1.4, None, Q, None, None) == _native.GAMER_EINVAL
+        assert f(P, 2, 2, 2, None, P, 1.4, None, Q, None, None) == _native.GAMER_EINVAL
+        assert f(P, 2, 2, 2, P, None, 1.4, None, Q, None, None) == _native.GAMER_EINVAL
+        assert f(P, 2, 2, 2, P, P, 1.4, None, None, None, None) == _native.GAMER_EINVAL
+        assert f(P, 2, 2, 2, P, P, 1.4, None, P, None, None) == _native.GAMER_EINVAL
+        assert b"different" in lib.gamer_last_error()
+        assert f(P, 2, 2, 2, P, P, 0.9, None, Q, None, None) == _native.GAMER_EINVAL
+        bad = _native.GamerOpts(1.5, 7, 0)
+        assert f(P, 2, 2, 2, P, P, 1.4, None, Q, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+        bad = _native.GamerOpts(3.0, 0, 0)
+        assert f(P, 2, 2, 2, P, P, 1.4, None, Q, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+
+
+def test_cf_face_struct_layout(tmp_path):
+    """gamer_cf_face as the C compiler lays it out equals the numpy record type
+    the binding builds (offsets and size), compiled from the public header."""
+    import subprocess
+    from paper_1007_3818_amd.amr import CF_FACE_DTYPE
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "gamer_hydro.h"\n'
+        "int main(void) { printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(gamer_cf_face),"
+        " offsetof(gamer_cf_face, coarse_group), offsetof(gamer_cf_face, fine_group),"
+        " offsetof(gamer_cf_face, dir), offsetof(gamer_cf_face, coarse_face),"
+        " offsetof(gamer_cf_face, side), offsetof(gamer_cf_face, qs), offsetof(gamer_cf_face, qf));"
+        " return 0; }\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    f = CF_FACE_DTYPE.fields
+    want = [CF_FACE_DTYPE.itemsize] + [f[n][1] for n in
+                                       ("coarse_group", "fine_group", "dir", "coarse_face", "side", "qs", "qf")]
+    assert got == want
+
+
+def test_amr_argument_errors(lib):
+    E = _native.GAMER_EINVAL
+    A16 = ctypes.c_void_p(0x1000)
+    A8 = ctypes.c_void_p(0x1008)
+    for f in (lib.gamer_flux_accumulate, lib.gamer_flux_accumulate_f32):
+        assert f(P, -1, P, 1, A16) == E
+        assert f(None, 0, None, 1, None) == _native.GAMER_OK
+        assert f(None, 2, P, 1, A16) == E
+        assert f(P, 2, None, 1, A16) == E
+        assert f(P, 2, P, 1, None) == E
+        assert f(P, 2, P, 1, A8) == E
+        assert b"aligned" in lib.gamer_last_error()
+    for f in (lib.gamer_flux_correct, lib.gamer_flux_correct_f32):
+        assert f(P, -1, P, P, 1, P, 1, P, P, None) == E
+        assert f(P, 1, P, P, -1, P, 1, P, P, None) == E
+        assert f(P, 1, P, P, 1, P, -5, P, P, None) == E
+        assert f(None, 1, None, None, 1, None, 0, None, None, None) == _native.GAMER_OK
+        assert f(None, 1, P, P, 1, P, 1, P, P, None) == E
+        assert f(P, 1, P, P, 1, None, 1, P, P, None) == E
+        assert f(P, 1, P, P, 1, P, 1, None, P, None) == E
+        assert f(P, 1, P, P, 1, P, 1, P, None, None) == E
+        assert f(P, 1, P, P, 1, ctypes.c_void_p(0x1004), 1, P, P, None) == E
+        assert f(P, 1, P, P, 1, P, (1 << 32) + 1, P, P, None) == E
+    for f in (lib.gamer_restrict, lib.gamer_restrict_f32):
+        assert f(P, P, -1, P, 1, None) == E
+        assert f(P, P, 1, P, -1, None) == E
+        assert f(P, P, (1 << 27) + 1, P, 1, None) == E
+        assert f(None, None, 0, None, 0, None) == _native.GAMER_OK
+        assert f(None, P, 1, P, 1, None) == E
+        assert f(P, None, 1, P, 1, None) == E
+        assert f(P, P, 1, None, 1, None) == E
 
 
 def test_other_entry_point_errors(lib):
