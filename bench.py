@@ -183,6 +183,28 @@ def bench_dtype(tag, state, g, dh, steps, warmup, shape=None):
 
     ms_fused = timed_loop(fused_step)
 
+    mixed = None
+    if tag == "f64":
+        # the same fused periodic step with FP64 state and FP32 arithmetic
+        if shape is None:
+            progress("f64: tuning the FP64-state, FP32-arithmetic periodic step")
+            mt = autotune.tune(out, dt_dev, dh_dev, GAMMA, use_cache=False, periodic=(g, g, g),
+                               compute=torch.float32)
+            mvariant, mgrid = mt["variant"], mt["grid"]
+        else:
+            mvariant, mgrid = 0, shape[1]
+
+        def mixed_step(cur, nxt):
+            hydro.hydro_solve_periodic(cur, g, g, g, dt_dev, dh_dev, GAMMA, out=nxt, group_stats=stats,
+                                       variant=mvariant, grid=mgrid, compute=torch.float32)
+            hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev, totals_out=totals)
+
+        ms_mixed = timed_loop(mixed_step)
+        mixed = {"ms_per_step": ms_mixed, "cell_updates_per_s": cells / (ms_mixed * 1e-3),
+                 "variant": mvariant, "grid": mgrid,
+                 "step": "fused periodic step, FP64 state, FP32 reconstruction/prediction/Riemann, "
+                         "FP64 update + reduce"}
+
     progress(f"{tag}: timing ghost-fill kernel + batched step")
 
     def packed_step(cur, nxt):
@@ -209,6 +231,7 @@ def bench_dtype(tag, state, g, dh, steps, warmup, shape=None):
                                    "grid evolving"},
         "with_ghost_fill": {"ms_per_step": ms_full, "cell_updates_per_s": cells / (ms_full * 1e-3),
                             "step": "periodic ghost fill + batched solve + reduce, grid evolving"},
+        **({"fp64_state_fp32_arithmetic": mixed} if mixed else {}),
     }
 
 

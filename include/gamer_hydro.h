@@ -77,7 +77,17 @@ typedef struct gamer_opts {
     /* Work-groups launched: 0 launches one per group; g > 0 launches
      * min(g, n_groups) persistent work-groups that stride over the groups. */
     int32_t grid;
+    /* Variables the slopes are limited in: GAMER_LIMIT_PRIMITIVE (0, the
+     * default) limits each primitive variable; GAMER_LIMIT_CHARACTERISTIC (1)
+     * limits the wave amplitudes of the primitive system's eigen-decomposition
+     * along each direction (the paper does not say which; both are common
+     * choices of the MUSCL-Hancock reconstruction step, Toro 2009, Sec. 14). */
+    int32_t limiting;
+    int32_t reserved; /* must be 0 */
 } gamer_opts;
+
+#define GAMER_LIMIT_PRIMITIVE 0
+#define GAMER_LIMIT_CHARACTERISTIC 1
 
 /* Number of compiled solver variants for the float (f32 != 0) or double path,
  * and the shape of variant v: work-group size in threads and the waves per
@@ -151,6 +161,24 @@ int gamer_hydro_solve_periodic(const double *state, int gx, int gy, int gz, cons
 int gamer_hydro_solve_periodic_f32(const float *state, int gx, int gy, int gz, const double *dt_dev,
                                    const double *dh_dev, double gamma, float *fluxes_out,
                                    float *state_out, double *group_stats, const gamer_opts *opts);
+
+/* ---- FP64 state, FP32 arithmetic ----------------------------------------
+ * The batched and periodic steps on double arrays with the reconstruction,
+ * prediction and Riemann solver evaluated in float, and the full-step update
+ * U - dt/dh * sum(dF) formed and stored in double: the state keeps FP64
+ * resolution (no float rounding of the state accumulates over steps) at about
+ * the FP32 arithmetic cost.  Arguments, layouts and errors as in
+ * gamer_hydro_solve_batched / gamer_hydro_solve_periodic with double arrays;
+ * fluxes_out holds the float fluxes widened to double; opts->variant indexes
+ * the float variants (gamer_solver_variants(1)). */
+int gamer_hydro_solve_batched_mixed(const double *groups_in, int64_t n_groups, const int8_t *level,
+                                    const double *dt_dev, const double *dh_dev, int n_levels,
+                                    double gamma, double *fluxes_out, double *groups_out,
+                                    double *group_stats, const gamer_opts *opts);
+int gamer_hydro_solve_periodic_mixed(const double *state, int gx, int gy, int gz,
+                                     const double *dt_dev, const double *dh_dev, double gamma,
+                                     double *fluxes_out, double *state_out, double *group_stats,
+                                     const gamer_opts *opts);
 
 /* ---- reduction of group stats to time steps and totals -----------------
  * From group_stats [n_groups][8] (as written by the batched step or by

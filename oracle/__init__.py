@@ -47,6 +47,10 @@ def _lib():
             "gamer_oracle_roe_flux": (ctypes.c_int, [_PD, _PD, ctypes.c_int, _D, _PD]),
             "gamer_oracle_roe_decompose": (None, [_PD, _PD, _D, _PD, _PD, _PD, _PD]),
             "gamer_oracle_hydro_solve": (ctypes.c_int, [_PD, _I64, _D, _D, _D, _D, _PD, _PD, _PLL]),
+            "gamer_oracle_hydro_solve_lim": (ctypes.c_int, [_PD, _I64, _D, _D, _D, _D, ctypes.c_int, _PD,
+                                                            _PD, _PLL]),
+            "gamer_oracle_char_slope": (None, [_PD, _PD, _PD, ctypes.c_int, _D, _D, _PD]),
+            "gamer_oracle_group_slopes_char": (None, [_PD, _D, _D, _PD]),
             "gamer_oracle_max_speed": (_D, [_PD, _I64, _D]),
             "gamer_oracle_cfl_dt": (_D, [_PD, _I64, _D, _D, _D]),
             "gamer_oracle_conserved_sums": (None, [_PD, _I64, _D, _PD]),
@@ -143,6 +147,22 @@ def group_slopes(W, theta=THETA):
     return dW
 
 
+def char_slope(Wc, a, b, d, gamma, theta=THETA):
+    """Limited slope of one cell along d in characteristic variables, from the
+    cell's primitive state and its one-sided primitive differences."""
+    Wc, a, b = _f64(Wc), _f64(a), _f64(b)
+    out = np.empty(5)
+    _lib().gamer_oracle_char_slope(_p(Wc), _p(a), _p(b), int(d), gamma, theta, _p(out))
+    return out
+
+
+def group_slopes_char(W, gamma, theta=THETA):
+    W = _f64(W)
+    dW = np.empty((3, 5, 18, 18, 18))
+    _lib().gamer_oracle_group_slopes_char(_p(W), gamma, theta, _p(dW))
+    return dW
+
+
 def group_predict(U, W, dW, dt, dh, gamma):
     U, W, dW = _f64(U), _f64(W), _f64(dW)
     Ub = np.empty((3, 2, 5, 18, 18, 18))
@@ -167,16 +187,18 @@ def group_update(U, Fl, dt, dh, want_planes=False):
 
 # --- batch entry points -----------------------------------------------------
 
-def hydro_solve(groups_in, dt, dh, gamma, theta=THETA, want_fluxes=False):
-    """One step on a batch.  Returns (groups_out, fluxes_or_None, (n_pred_fallback, n_hlle))."""
+def hydro_solve(groups_in, dt, dh, gamma, theta=THETA, want_fluxes=False, limiting="primitive"):
+    """One step on a batch.  Returns (groups_out, fluxes_or_None, (n_pred_fallback, n_hlle)).
+    limiting: "primitive" or "characteristic" (variables the slopes are limited in)."""
+    char = {"primitive": 0, "characteristic": 1}[limiting]
     g = _f64(groups_in)
     assert g.ndim == 5 and g.shape[1:] == (5, 20, 20, 20), g.shape
     n = g.shape[0]
     out = np.empty((n, 5, 16, 16, 16))
     fl = np.empty((n, 3, 3, 5, 16, 16)) if want_fluxes else None
     counts = (ctypes.c_longlong * 2)()
-    rc = _lib().gamer_oracle_hydro_solve(_p(g), n, dt, dh, gamma, theta, _p(fl), _p(out),
-                                         ctypes.cast(counts, _PLL))
+    rc = _lib().gamer_oracle_hydro_solve_lim(_p(g), n, dt, dh, gamma, theta, char, _p(fl), _p(out),
+                                             ctypes.cast(counts, _PLL))
     if rc != 0:
         raise ValueError("oracle hydro_solve rejected its arguments")
     return out, fl, (int(counts[0]), int(counts[1]))
@@ -230,7 +252,8 @@ def pack_periodic_subset(state, gx, gy, gz, ids):
     return out
 
 
-def step_periodic(state, gx, gy, gz, dt, dh, gamma, theta=THETA):
+def step_periodic(state, gx, gy, gz, dt, dh, gamma, theta=THETA, limiting="primitive"):
     """Ghost fill then one step of a uniform periodic grid held as groups."""
-    out, _, counts = hydro_solve(pack_periodic(state, gx, gy, gz), dt, dh, gamma, theta)
+    out, _, counts = hydro_solve(pack_periodic(state, gx, gy, gz), dt, dh, gamma, theta,
+                                 limiting=limiting)
     return out, counts

@@ -178,6 +178,71 @@ void gamer_oracle_group_slopes(const double *W, double theta, double *dW) {
             }
 }
 
+/* Limited slope of one cell along direction d in characteristic variables
+ * (limiting variant): the one-sided primitive differences a = W_c - W_{c-1}
+ * and b = W_{c+1} - W_c are projected onto the left eigenvectors of the
+ * primitive-variable system along d, evaluated at W_c; each wave's two
+ * projections are limited with the generalised minmod; the limited wave
+ * amplitudes are mapped back with the right eigenvectors (Toro 2009, Sec. 14
+ * notes limiting in characteristic variables; the eigenvectors are those of
+ * the quasi-linear primitive system, Toro 2009, Sec. 3.2).  With n the normal
+ * velocity component, t1, t2 the transverse ones, c^2 = gamma p / rho:
+ *   wave u - c:  l = (0, -rho/(2c), 0, 0, 1/(2c^2)),  r = (1, -c/rho, 0, 0, c^2)
+ *   wave u (entropy):  l = (1, 0, 0, 0, -1/c^2),      r = (1, 0, 0, 0, 0)
+ *   waves u (shear): l = r = unit vectors of t1, t2
+ *   wave u + c:  l = (0, rho/(2c), 0, 0, 1/(2c^2)),   r = (1, c/rho, 0, 0, c^2)
+ * (vector components in the order rho, n, t1, t2, p). */
+void gamer_oracle_char_slope(const double *Wc, const double *a, const double *b, int d, double g,
+                             double theta, double *dW) {
+    const int n = 1 + d, t1 = d == 0 ? 2 : 1, t2 = d == 2 ? 2 : 3;
+    const double rho = Wc[0];
+    const double c2 = g * Wc[4] / rho;
+    const double c = sqrt(c2);
+    double la[5], lb[5], m[5];
+    la[0] = -rho / (2.0 * c) * a[n] + a[4] / (2.0 * c2);
+    lb[0] = -rho / (2.0 * c) * b[n] + b[4] / (2.0 * c2);
+    la[1] = a[0] - a[4] / c2;
+    lb[1] = b[0] - b[4] / c2;
+    la[2] = a[t1];
+    lb[2] = b[t1];
+    la[3] = a[t2];
+    lb[3] = b[t2];
+    la[4] = rho / (2.0 * c) * a[n] + a[4] / (2.0 * c2);
+    lb[4] = rho / (2.0 * c) * b[n] + b[4] / (2.0 * c2);
+    for (int w = 0; w < 5; ++w) m[w] = gamer_oracle_limiter(la[w], lb[w], theta);
+    dW[0] = m[0] + m[1] + m[4];
+    dW[n] = c / rho * (m[4] - m[0]);
+    dW[t1] = m[2];
+    dW[t2] = m[3];
+    dW[4] = c2 * (m[0] + m[4]);
+}
+
+/* Limited slopes in characteristic variables on the face-state set; layout
+ * as gamer_oracle_group_slopes. */
+void gamer_oracle_group_slopes_char(const double *W, double g, double theta, double *dW) {
+    const size_t plane = (size_t)NV * NF * NF * NF;
+    memset(dW, 0, 3 * plane * sizeof(double));
+    for (int k = -1; k <= NI; ++k)
+        for (int j = -1; j <= NI; ++j)
+            for (int i = -1; i <= NI; ++i) {
+                if (!in_face_state_set(i, j, k)) continue;
+                double wc[NV];
+                for (int v = 0; v < NV; ++v) wc[v] = W[ip(v, i, j, k)];
+                for (int d = 0; d < 3; ++d) {
+                    int im = i, jm = j, km = k, iq = i, jq = j, kq = k;
+                    neighbour(d, -1, &im, &jm, &km);
+                    neighbour(d, +1, &iq, &jq, &kq);
+                    double a[NV], b[NV], out[NV];
+                    for (int v = 0; v < NV; ++v) {
+                        a[v] = wc[v] - W[ip(v, im, jm, km)];
+                        b[v] = W[ip(v, iq, jq, kq)] - wc[v];
+                    }
+                    gamer_oracle_char_slope(wc, a, b, d, g, theta, out);
+                    for (int v = 0; v < NV; ++v) dW[d * plane + is(v, i, j, k)] = out[v];
+                }
+            }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Step 2: half-step prediction (conservative Hancock step, unsplit).      */
 
@@ -505,9 +570,22 @@ void gamer_oracle_group_update(const double *U, const double *Fl, double dt, dou
  * fluxes_out: [n][3][3][5][16][16] or NULL; counts: [2] or NULL receives
  * (predictor fallbacks, HLLE fallbacks) summed over the batch.
  * Returns 0, or -1 on invalid arguments / allocation failure. */
+int gamer_oracle_hydro_solve_lim(const double *groups_in, int64_t n_groups, double dt, double dh,
+                                 double gamma, double theta, int char_limiting, double *fluxes_out,
+                                 double *groups_out, long long *counts);
+
 int gamer_oracle_hydro_solve(const double *groups_in, int64_t n_groups, double dt, double dh,
                              double gamma, double theta, double *fluxes_out, double *groups_out,
                              long long *counts) {
+    return gamer_oracle_hydro_solve_lim(groups_in, n_groups, dt, dh, gamma, theta, 0, fluxes_out,
+                                        groups_out, counts);
+}
+
+/* As gamer_oracle_hydro_solve; char_limiting != 0 takes the slopes in
+ * characteristic variables (gamer_oracle_group_slopes_char). */
+int gamer_oracle_hydro_solve_lim(const double *groups_in, int64_t n_groups, double dt, double dh,
+                                 double gamma, double theta, int char_limiting, double *fluxes_out,
+                                 double *groups_out, long long *counts) {
     if (n_groups < 0 || (n_groups > 0 && (!groups_in || !groups_out))) return -1;
     if (!(dt > 0.0) || !(dh > 0.0) || !(gamma > 1.0)) return -1;
     const size_t in_sz = (size_t)NV * NP * NP * NP;
@@ -535,7 +613,10 @@ int gamer_oracle_hydro_solve(const double *groups_in, int64_t n_groups, double d
             if (!ok) continue;
             const double *U = groups_in + (size_t)gi * in_sz;
             gamer_oracle_group_prim(U, gamma, W);
-            gamer_oracle_group_slopes(W, theta, dW);
+            if (char_limiting)
+                gamer_oracle_group_slopes_char(W, gamma, theta, dW);
+            else
+                gamer_oracle_group_slopes(W, theta, dW);
             bad_pred += gamer_oracle_group_predict(U, W, dW, dt, dh, gamma, Ub);
             bad_roe += gamer_oracle_group_fluxes(Ub, gamma, Fl);
             gamer_oracle_group_update(U, Fl, dt, dh, groups_out + (size_t)gi * out_sz,

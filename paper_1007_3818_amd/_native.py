@@ -22,8 +22,13 @@ _I = ctypes.c_int
 _I64 = ctypes.c_int64
 
 
+LIMIT_PRIMITIVE = 0
+LIMIT_CHARACTERISTIC = 1
+
+
 class GamerOpts(ctypes.Structure):
-    _fields_ = [("theta", ctypes.c_double), ("variant", ctypes.c_int32), ("grid", ctypes.c_int32)]
+    _fields_ = [("theta", ctypes.c_double), ("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("limiting", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _PO = ctypes.POINTER(GamerOpts)
@@ -42,6 +47,8 @@ SIGNATURES = {
     "gamer_hydro_solve_batched_f32": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO]),
     "gamer_hydro_solve_periodic": (_I, [_P, _I, _I, _I, _P, _P, _D, _P, _P, _P, _PO]),
     "gamer_hydro_solve_periodic_f32": (_I, [_P, _I, _I, _I, _P, _P, _D, _P, _P, _P, _PO]),
+    "gamer_hydro_solve_batched_mixed": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO]),
+    "gamer_hydro_solve_periodic_mixed": (_I, [_P, _I, _I, _I, _P, _P, _D, _P, _P, _P, _PO]),
     "gamer_step_reduce": (_I, [_P, _I64, _P, _P, _I, _D, _P, _P]),
     "gamer_group_stats": (_I, [_P, _I64, _D, _P]),
     "gamer_group_stats_f32": (_I, [_P, _I64, _D, _P]),

@@ -25,14 +25,18 @@ def cache_path() -> str:
         os.path.expanduser("~"), ".cache", "gamer_hydro", "tune.json")
 
 
-def _key(dtype, n_groups: int, periodic: bool = False) -> str:
+def _key(dtype, n_groups: int, periodic: bool = False, compute=None) -> str:
     name = torch.cuda.get_device_name(0)
     bucket = 1 << max(0, (int(n_groups) - 1).bit_length())
     kind = "|periodic" if periodic else ""
-    return f"{name}|{'f32' if dtype == torch.float32 else 'f64'}|{bucket}{kind}"
+    prec = "f32" if dtype == torch.float32 else "f64"
+    if compute is not None and compute != dtype:
+        prec += "-f32compute"
+    return f"{name}|{prec}|{bucket}{kind}"
 
 
 def candidates(dtype, n_groups: int):
+    """(variant, grid) pairs for arithmetic dtype `dtype`."""
     n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     grids = [0] + [n_cu * k for k in (1, 2, 3, 4) if n_cu * k < n_groups]
     # compiled variants x grids
@@ -71,11 +75,13 @@ def max_rel_diff(a: torch.Tensor, b: torch.Tensor) -> float:
 
 
 def tune(padded: torch.Tensor, dt_dev: torch.Tensor, dh_dev: torch.Tensor, gamma: float,
-         level=None, reps: int = 5, use_cache: bool = True, periodic=None) -> dict:
+         level=None, reps: int = 5, use_cache: bool = True, periodic=None, compute=None) -> dict:
     """Return {"variant", "grid", "ms", "table"} for this batch.  With
     ``periodic=(gx, gy, gz)``, ``padded`` is instead the interior state of a
-    periodic grid and the fused periodic step is tuned."""
-    key = _key(padded.dtype, padded.shape[0], periodic is not None)
+    periodic grid and the fused periodic step is tuned; ``compute`` as in
+    hydro.hydro_solve_batched."""
+    key = _key(padded.dtype, padded.shape[0], periodic is not None, compute)
+    cdt = compute if compute is not None else padded.dtype
     if use_cache:
         hit = _load().get(key)
         if hit is not None:
@@ -85,21 +91,22 @@ def tune(padded: torch.Tensor, dt_dev: torch.Tensor, dh_dev: torch.Tensor, gamma
 
     def run(v, g):
         if periodic is None:
-            hydro.hydro_solve_batched(padded, level, dt_dev, dh_dev, gamma, out=out, variant=v, grid=g)
+            hydro.hydro_solve_batched(padded, level, dt_dev, dh_dev, gamma, out=out, variant=v, grid=g,
+                                      compute=compute)
         else:
             hydro.hydro_solve_periodic(padded, *periodic, dt_dev, dh_dev, gamma, out=out, variant=v,
-                                       grid=g)
+                                       grid=g, compute=compute)
 
     ref = None
     table = []
-    for v, g in candidates(padded.dtype, n):
+    for v, g in candidates(cdt, n):
         run(v, g)
         torch.cuda.synchronize()
         if ref is None:
             ref = out.clone()
         else:
             err = max_rel_diff(out, ref)
-            if not err <= (1e-6 if padded.dtype == torch.float32 else 1e-13):
+            if not err <= (1e-6 if cdt == torch.float32 else 1e-13):
                 raise RuntimeError(f"solver variant {v} grid {g} differs from variant 0 by {err:.3e}: "
                                    "refusing to tune")
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -108,7 +115,7 @@ def tune(padded: torch.Tensor, dt_dev: torch.Tensor, dh_dev: torch.Tensor, gamma
             run(v, g)
         ev[1].record()
         torch.cuda.synchronize()
-        th, wv = hydro.solver_variants(padded.dtype)[v]
+        th, wv = hydro.solver_variants(cdt)[v]
         table.append({"variant": v, "threads": th, "waves_per_simd": wv,
                       "grid": g, "ms": ev[0].elapsed_time(ev[1]) / reps})
     best = min(table, key=lambda r: r["ms"])

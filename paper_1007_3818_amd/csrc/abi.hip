@@ -64,20 +64,35 @@ int scratch(size_t bytes, void **out) {
     return GAMER_OK;
 }
 
+// Tunables shared by the solver entry points; returns GAMER_OK or an error.
 template <typename T>
-int solve_common(const T *in, int64_t n, const int8_t *level, const double *dt_dev,
+int parse_opts(const gamer_opts *opts, double *theta, int *variant, int64_t *grid, int *limiting) {
+    *theta = (opts && opts->theta != 0.0) ? opts->theta : 1.5;
+    if (!(*theta >= 1.0 && *theta <= 2.0)) return fail(GAMER_EINVAL, "theta must lie in [1, 2]");
+    *variant = opts ? opts->variant : 0;
+    *grid = opts ? opts->grid : 0;
+    *limiting = opts ? opts->limiting : 0;
+    if (*variant < 0 || *variant >= solve_variant_count<T>())
+        return fail(GAMER_EINVAL, "variant must lie in [0, %d)", solve_variant_count<T>());
+    if (*grid < 0) return fail(GAMER_EINVAL, "grid must be >= 0");
+    if (*limiting != GAMER_LIMIT_PRIMITIVE && *limiting != GAMER_LIMIT_CHARACTERISTIC)
+        return fail(GAMER_EINVAL, "limiting must be GAMER_LIMIT_PRIMITIVE or GAMER_LIMIT_CHARACTERISTIC");
+    if (opts && opts->reserved != 0) return fail(GAMER_EINVAL, "gamer_opts.reserved must be 0");
+    return GAMER_OK;
+}
+
+// Storage type S (the arrays), arithmetic type T.
+template <typename S, typename T>
+int solve_common(const S *in, int64_t n, const int8_t *level, const double *dt_dev,
                  const double *dh_dev, int n_levels, double dt, double dh, double gamma,
-                 T *fluxes, T *out, double *stats, const gamer_opts *opts) {
+                 S *fluxes, S *out, double *stats, const gamer_opts *opts) {
     g_err[0] = 0;
     if (n < 0) return fail(GAMER_EINVAL, "n_groups < 0");
     if (!(isfinite(gamma) && gamma > 1.0)) return fail(GAMER_EINVAL, "gamma must be > 1");
-    const double theta = (opts && opts->theta != 0.0) ? opts->theta : 1.5;
-    if (!(theta >= 1.0 && theta <= 2.0)) return fail(GAMER_EINVAL, "theta must lie in [1, 2]");
-    const int variant = opts ? opts->variant : 0;
-    const int64_t grid = opts ? opts->grid : 0;
-    if (variant < 0 || variant >= solve_variant_count<T>())
-        return fail(GAMER_EINVAL, "variant must lie in [0, %d)", solve_variant_count<T>());
-    if (grid < 0) return fail(GAMER_EINVAL, "grid must be >= 0");
+    double theta;
+    int variant, limiting;
+    int64_t grid;
+    if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting)) return e;
     if (!dt_dev && (!finite_pos(dt) || !finite_pos(dh)))
         return fail(GAMER_EINVAL, "dt and dh must be finite and positive");
     if (n == 0) return GAMER_OK;
@@ -85,7 +100,7 @@ int solve_common(const T *in, int64_t n, const int8_t *level, const double *dt_d
     if (dt_dev && !dh_dev) return fail(GAMER_EINVAL, "NULL dh_dev");
     if (dt_dev && (n_levels < 1 || n_levels > GAMER_MAX_LEVELS))
         return fail(GAMER_EINVAL, "n_levels must lie in [1, %d]", GAMER_MAX_LEVELS);
-    SolveParams<T> p;
+    SolveParams<S> p;
     p.in = in;
     p.gx = p.gy = p.gz = 0;
     p.out = out;
@@ -99,12 +114,13 @@ int solve_common(const T *in, int64_t n, const int8_t *level, const double *dt_d
     p.gamma = gamma;
     p.theta = theta;
     p.n_groups = n;
-    return check_hip(launch_solve<T>(p, variant, grid, g_stream), "solver launch");
+    p.char_limiting = limiting;
+    return check_hip(launch_solve<S, T>(p, variant, grid, g_stream), "solver launch");
 }
 
-template <typename T>
-int periodic_common(const T *state, int gx, int gy, int gz, const double *dt_dev,
-                    const double *dh_dev, double gamma, T *fluxes, T *out, double *stats,
+template <typename S, typename T>
+int periodic_common(const S *state, int gx, int gy, int gz, const double *dt_dev,
+                    const double *dh_dev, double gamma, S *fluxes, S *out, double *stats,
                     const gamer_opts *opts) {
     g_err[0] = 0;
     if (gx < 1 || gy < 1 || gz < 1) return fail(GAMER_EINVAL, "gx, gy, gz must be >= 1");
@@ -116,14 +132,11 @@ int periodic_common(const T *state, int gx, int gy, int gz, const double *dt_dev
     if (static_cast<const void *>(state) == static_cast<const void *>(out))
         return fail(GAMER_EINVAL, "state and state_out must be different arrays");
     if (!(isfinite(gamma) && gamma > 1.0)) return fail(GAMER_EINVAL, "gamma must be > 1");
-    const double theta = (opts && opts->theta != 0.0) ? opts->theta : 1.5;
-    if (!(theta >= 1.0 && theta <= 2.0)) return fail(GAMER_EINVAL, "theta must lie in [1, 2]");
-    const int variant = opts ? opts->variant : 0;
-    const int64_t grid = opts ? opts->grid : 0;
-    if (variant < 0 || variant >= solve_variant_count<T>())
-        return fail(GAMER_EINVAL, "variant must lie in [0, %d)", solve_variant_count<T>());
-    if (grid < 0) return fail(GAMER_EINVAL, "grid must be >= 0");
-    SolveParams<T> p;
+    double theta;
+    int variant, limiting;
+    int64_t grid;
+    if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting)) return e;
+    SolveParams<S> p;
     p.in = state;
     p.gx = gx;
     p.gy = gy;
@@ -138,7 +151,8 @@ int periodic_common(const T *state, int gx, int gy, int gz, const double *dt_dev
     p.gamma = gamma;
     p.theta = theta;
     p.n_groups = n;
-    return check_hip(launch_solve<T>(p, variant, grid, g_stream), "solver launch");
+    p.char_limiting = limiting;
+    return check_hip(launch_solve<S, T>(p, variant, grid, g_stream), "solver launch");
 }
 
 template <typename T>
@@ -291,13 +305,13 @@ int gamer_solver_variant_shape(int f32, int variant, int *threads, int *waves_pe
 
 int gamer_hydro_solve(const double *groups_in, int64_t n_groups, double dt, double dh,
                       double gamma, double *fluxes_out, double *groups_out) {
-    return solve_common<double>(groups_in, n_groups, nullptr, nullptr, nullptr, 1, dt, dh, gamma,
+    return solve_common<double, double>(groups_in, n_groups, nullptr, nullptr, nullptr, 1, dt, dh, gamma,
                                 fluxes_out, groups_out, nullptr, nullptr);
 }
 
 int gamer_hydro_solve_f32(const float *groups_in, int64_t n_groups, double dt, double dh,
                           double gamma, float *fluxes_out, float *groups_out) {
-    return solve_common<float>(groups_in, n_groups, nullptr, nullptr, nullptr, 1, dt, dh, gamma,
+    return solve_common<float, float>(groups_in, n_groups, nullptr, nullptr, nullptr, 1, dt, dh, gamma,
                                fluxes_out, groups_out, nullptr, nullptr);
 }
 
@@ -306,8 +320,8 @@ int gamer_hydro_solve_batched(const double *groups_in, int64_t n_groups, const i
                               double gamma, double *fluxes_out, double *groups_out,
                               double *group_stats, const gamer_opts *opts) {
     if (!dt_dev && n_groups > 0) return fail(GAMER_EINVAL, "NULL dt_dev");
-    return solve_common<double>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, 0.0, 0.0,
-                                gamma, fluxes_out, groups_out, group_stats, opts);
+    return solve_common<double, double>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, 0.0,
+                                        0.0, gamma, fluxes_out, groups_out, group_stats, opts);
 }
 
 int gamer_hydro_solve_batched_f32(const float *groups_in, int64_t n_groups, const int8_t *level,
@@ -315,22 +329,39 @@ int gamer_hydro_solve_batched_f32(const float *groups_in, int64_t n_groups, cons
                                   double gamma, float *fluxes_out, float *groups_out,
                                   double *group_stats, const gamer_opts *opts) {
     if (!dt_dev && n_groups > 0) return fail(GAMER_EINVAL, "NULL dt_dev");
-    return solve_common<float>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, 0.0, 0.0,
+    return solve_common<float, float>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, 0.0, 0.0,
                                gamma, fluxes_out, groups_out, group_stats, opts);
 }
 
 int gamer_hydro_solve_periodic(const double *state, int gx, int gy, int gz, const double *dt_dev,
                                const double *dh_dev, double gamma, double *fluxes_out,
                                double *state_out, double *group_stats, const gamer_opts *opts) {
-    return periodic_common<double>(state, gx, gy, gz, dt_dev, dh_dev, gamma, fluxes_out, state_out,
+    return periodic_common<double, double>(state, gx, gy, gz, dt_dev, dh_dev, gamma, fluxes_out, state_out,
                                    group_stats, opts);
 }
 
 int gamer_hydro_solve_periodic_f32(const float *state, int gx, int gy, int gz, const double *dt_dev,
                                    const double *dh_dev, double gamma, float *fluxes_out,
                                    float *state_out, double *group_stats, const gamer_opts *opts) {
-    return periodic_common<float>(state, gx, gy, gz, dt_dev, dh_dev, gamma, fluxes_out, state_out,
+    return periodic_common<float, float>(state, gx, gy, gz, dt_dev, dh_dev, gamma, fluxes_out, state_out,
                                   group_stats, opts);
+}
+
+int gamer_hydro_solve_batched_mixed(const double *groups_in, int64_t n_groups, const int8_t *level,
+                                    const double *dt_dev, const double *dh_dev, int n_levels,
+                                    double gamma, double *fluxes_out, double *groups_out,
+                                    double *group_stats, const gamer_opts *opts) {
+    if (!dt_dev && n_groups > 0) return fail(GAMER_EINVAL, "NULL dt_dev");
+    return solve_common<double, float>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, 0.0, 0.0,
+                                       gamma, fluxes_out, groups_out, group_stats, opts);
+}
+
+int gamer_hydro_solve_periodic_mixed(const double *state, int gx, int gy, int gz,
+                                     const double *dt_dev, const double *dh_dev, double gamma,
+                                     double *fluxes_out, double *state_out, double *group_stats,
+                                     const gamer_opts *opts) {
+    return periodic_common<double, float>(state, gx, gy, gz, dt_dev, dh_dev, gamma, fluxes_out,
+                                          state_out, group_stats, opts);
 }
 
 int gamer_step_reduce(const double *group_stats, int64_t n_groups, const int8_t *level,

@@ -38,6 +38,7 @@ struct SolveParams {
     double dt, dh;
     double gamma, theta;
     int64_t n_groups;
+    int char_limiting;  // 0: limit primitive variables, 1: characteristic variables
 };
 
 // Compiled solver variants (work-group size, occupancy target) and the launcher.
@@ -45,8 +46,10 @@ template <typename T>
 int solve_variant_count();
 template <typename T>
 int solve_variant_shape(int variant, int *threads, int *waves_per_simd);
-template <typename T>
-hipError_t launch_solve(const SolveParams<T> &p, int variant, int64_t grid, hipStream_t s);
+// Storage type S (the arrays of P), arithmetic type T: <float, float>,
+// <double, double>, or <double, float> (FP64 state, FP32 arithmetic).
+template <typename S, typename T>
+hipError_t launch_solve(const SolveParams<S> &p, int variant, int64_t grid, hipStream_t s);
 
 template <typename T>
 hipError_t launch_pack_periodic(const T *state, int gx, int gy, int gz, T *padded, hipStream_t s);

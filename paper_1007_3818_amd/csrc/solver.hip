@@ -62,6 +62,30 @@ __device__ __forceinline__ double limiter(double a, double b, double theta) {
     return a > 0.0 ? m : -m;
 }
 
+// Limited slope along direction D in characteristic variables: the one-sided
+// primitive differences a, b are projected on the left eigenvectors of the
+// primitive system along D at the cell state, each wave's pair is limited,
+// and the limited amplitudes are mapped back with the right eigenvectors.
+// Component order (rho, normal velocity, two transverse velocities, p):
+//   u - c: l = (0, -rho/2c, 0, 0, 1/2c^2), r = (1, -c/rho, 0, 0, c^2)
+//   u (entropy): l = (1, 0, 0, 0, -1/c^2), r = (1, 0, 0, 0, 0)
+//   u (shear, two): unit vectors of the transverse velocities
+//   u + c: l = (0, rho/2c, 0, 0, 1/2c^2), r = (1, c/rho, 0, 0, c^2)
+// h = rho/(2c), q = 1/(2c^2), cr = c/rho, c2 = c^2 of the cell.
+template <int D, typename T>
+__device__ __forceinline__ void char_slope(const T a[NV], const T b[NV], T h, T q, T cr, T c2,
+                                           T theta, T dw[NV]) {
+    constexpr int N = 1 + D, T1 = D == 0 ? 2 : 1, T2 = D == 2 ? 2 : 3;
+    const T m0 = limiter(q * a[4] - h * a[N], q * b[4] - h * b[N], theta);
+    const T m1 = limiter(a[0] - T(2) * q * a[4], b[0] - T(2) * q * b[4], theta);
+    const T m4 = limiter(q * a[4] + h * a[N], q * b[4] + h * b[N], theta);
+    dw[0] = m0 + m1 + m4;
+    dw[N] = cr * (m4 - m0);
+    dw[T1] = limiter(a[T1], b[T1], theta);
+    dw[T2] = limiter(a[T2], b[T2], theta);
+    dw[4] = c2 * (m0 + m4);
+}
+
 // Physical flux along direction D of a primitive state (rho, u_x, u_y, u_z, p).
 template <int D, typename T>
 __device__ __forceinline__ void flux_prim(const T w[NV], const Consts<T> &c, T f[NV]) {
@@ -342,9 +366,9 @@ __device__ __forceinline__ void ring_cell(int r, int &ci, int &cj) {
 //  NT = 256: threads own the interior columns; in plane k the wave k mod 4 also
 //            computes the 64 ghost-layer cells in a second round (4 waves, one
 //            per SIMD).
-template <typename T, int NT, int WAVES, bool PERIODIC>
+template <typename S_, typename T, int NT, int WAVES, bool PERIODIC, bool CHAR>
 __global__ __attribute__((amdgpu_flat_work_group_size(NT, NT), amdgpu_waves_per_eu(WAVES, 8)))
-void solve_kernel(SolveParams<T> P) {
+void solve_kernel(SolveParams<S_> P) {
     static_assert(NT == 320 || NT == 256, "work-group shape");
     constexpr bool SPLIT = NT == 320;
     __shared__ Lds<T> S;
@@ -392,14 +416,14 @@ void solve_kernel(SolveParams<T> P) {
             return (Y % NI) * NI + (X % NI);
         };
         // z part, and the base pointer of a plane for the x/y group part 0
-        auto plane_base = [&](int kp) -> const T * {
+        auto plane_base = [&](int kp) -> const S_ * {
             if (!PERIODIC) return P.in + g * GIN + kp * NPL;
             int Z = bz * NI + kp - NG;
             const int NZ = P.gz * NI;
             Z = Z < 0 ? Z + NZ : (Z >= NZ ? Z - NZ : Z);
             return P.in + int64_t(P.gx) * P.gy * (Z / NI) * GOUT + (Z % NI) * (NI * NI);
         };
-        auto cell_ptr = [&](int ip, int jp, int kp) -> const T * {
+        auto cell_ptr = [&](int ip, int jp, int kp) -> const S_ * {
             int gp;
             const int cp = xy_part(ip, jp, gp);
             return plane_base(kp) + int64_t(gp) * GOUT + cp;
@@ -413,13 +437,13 @@ void solve_kernel(SolveParams<T> P) {
         const int cp1 = has1 ? xy_part(p1 % NP, p1 / NP, gp1) : cp0;
         T pre0[NV], pre1[NV];
         auto fetch = [&](int plane) {  // plane in -2..17
-            const T *src = plane_base(plane + NG);
-            const T *s0 = src + int64_t(gp0) * GOUT + cp0;
-            const T *s1 = src + int64_t(gp1) * GOUT + cp1;
+            const S_ *src = plane_base(plane + NG);
+            const S_ *s0 = src + int64_t(gp0) * GOUT + cp0;
+            const S_ *s1 = src + int64_t(gp1) * GOUT + cp1;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                pre0[v] = s0[v * VSTRIDE];
-                pre1[v] = has1 ? s1[v * VSTRIDE] : T(1);
+                pre0[v] = T(s0[v * VSTRIDE]);
+                pre1[v] = has1 ? T(s1[v * VSTRIDE]) : T(1);
             }
         };
         auto store = [&](int plane) {  // prefetched conserved -> primitive LDS plane
@@ -492,13 +516,42 @@ void solve_kernel(SolveParams<T> P) {
                 }
                 const int pos = (cj + NG) * NP + (ci + NG);
                 T W0[NV], dW[3][NV];
+                if constexpr (!CHAR) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    const T q0 = w0[v][pos];
-                    W0[v] = q0;
-                    dW[0][v] = limiter(q0 - w0[v][pos - 1], w0[v][pos + 1] - q0, c.theta);
-                    dW[1][v] = limiter(q0 - w0[v][pos - NP], w0[v][pos + NP] - q0, c.theta);
-                    dW[2][v] = limiter(q0 - wm[v][pos], wq[v][pos] - q0, c.theta);
+                    for (int v = 0; v < NV; ++v) {
+                        const T q0 = w0[v][pos];
+                        W0[v] = q0;
+                        dW[0][v] = limiter(q0 - w0[v][pos - 1], w0[v][pos + 1] - q0, c.theta);
+                        dW[1][v] = limiter(q0 - w0[v][pos - NP], w0[v][pos + NP] - q0, c.theta);
+                        dW[2][v] = limiter(q0 - wm[v][pos], wq[v][pos] - q0, c.theta);
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) W0[v] = w0[v][pos];
+                    const T c2 = c.g * W0[4] * rcp(W0[0]);
+                    const T ic = rsq(c2);                    // 1/c
+                    const T h = c.half * W0[0] * ic;         // rho/(2c)
+                    const T q = c.half * ic * ic;            // 1/(2c^2)
+                    const T cr = c2 * ic * rcp(W0[0]);       // c/rho
+                    T a[NV], b[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        a[v] = W0[v] - w0[v][pos - 1];
+                        b[v] = w0[v][pos + 1] - W0[v];
+                    }
+                    char_slope<0>(a, b, h, q, cr, c2, c.theta, dW[0]);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        a[v] = W0[v] - w0[v][pos - NP];
+                        b[v] = w0[v][pos + NP] - W0[v];
+                    }
+                    char_slope<1>(a, b, h, q, cr, c2, c.theta, dW[1]);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        a[v] = W0[v] - wm[v][pos];
+                        b[v] = wq[v][pos] - W0[v];
+                    }
+                    char_slope<2>(a, b, h, q, cr, c2, c.theta, dW[2]);
                 }
                 // predicted face states Ubar^{d,+-} = cons(W0 +- dW_d/2) + S
                 T Ub[3][2][NV];
@@ -507,7 +560,7 @@ void solve_kernel(SolveParams<T> P) {
                     ++n_pred;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        const T u0 = cell_ptr(ci + NG, cj + NG, k + NG)[v * VSTRIDE];
+                        const T u0 = T(cell_ptr(ci + NG, cj + NG, k + NG)[v * VSTRIDE]);
 #pragma unroll
                         for (int d = 0; d < 3; ++d) Ub[d][0][v] = Ub[d][1][v] = u0;
                     }
@@ -554,9 +607,9 @@ void solve_kernel(SolveParams<T> P) {
             if (inner && k >= 0) {
                 n_roe += roe_dir<2>(zp, zm, c, fzn);
                 if (P.flux && (k & 7) == 0) {
-                    T *dst = P.flux + g * GFLX + ((2 * 3 + (k >> 3)) * NV) * NINNER + jj * NI + ii;
+                    S_ *dst = P.flux + g * GFLX + ((2 * 3 + (k >> 3)) * NV) * NINNER + jj * NI + ii;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = fzn[v];
+                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(fzn[v]);
                 }
             }
             __syncthreads();  // B2: +x / +y states visible
@@ -588,9 +641,9 @@ void solve_kernel(SolveParams<T> P) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) S.sx[v][row][f] = F[v];
                     if (P.flux && (f & 7) == 0) {
-                        T *dst = P.flux + g * GFLX + ((0 * 3 + (f >> 3)) * NV) * NINNER + k * NI + row;
+                        S_ *dst = P.flux + g * GFLX + ((0 * 3 + (f >> 3)) * NV) * NINNER + k * NI + row;
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = F[v];
+                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(F[v]);
                     }
                 }
                 // y faces: face cj of each interior cell, then face 16 of each column
@@ -619,9 +672,9 @@ void solve_kernel(SolveParams<T> P) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) S.sy[v][f][col] = F[v];
                     if (P.flux && (f & 7) == 0) {
-                        T *dst = P.flux + g * GFLX + ((1 * 3 + (f >> 3)) * NV) * NINNER + k * NI + col;
+                        S_ *dst = P.flux + g * GFLX + ((1 * 3 + (f >> 3)) * NV) * NINNER + k * NI + col;
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = F[v];
+                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(F[v]);
                     }
                 }
             }
@@ -631,16 +684,16 @@ void solve_kernel(SolveParams<T> P) {
                 if (k >= 1) {
                     // plane k-1 is complete: U - dt/dh ((dF_x + dF_y) + dF_z)
                     const int kk = k - 1;
-                    T *dst = P.out + g * GOUT + kk * NINNER + t;
-                    const T *src = cell_ptr(ii + NG, jj + NG, kk + NG);
+                    S_ *dst = P.out + g * GOUT + kk * NINNER + t;
+                    const S_ *src = cell_ptr(ii + NG, jj + NG, kk + NG);
                     T un[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         const double dfz = double(fzn[v]) - double(fz[v]);
                         const double r = double(src[v * VSTRIDE]) - dtdh * (S.dxy[v][t] + dfz);
-                        const T o = T(r);
+                        const S_ o = S_(r);
                         dst[v * NI * NINNER] = o;
-                        un[v] = o;
+                        un[v] = T(o);
                         st[v] += double(o);
                     }
                     st[5] = fmax(st[5], double(signal_speed(un[0], un[1], un[2], un[3], un[4], c)));
@@ -691,33 +744,41 @@ int solve_variant_shape(int v, int *threads, int *waves) {
 }
 
 namespace {
-template <typename T, int V>
-void launch_variant(const SolveParams<T> &p, dim3 blocks, hipStream_t s) {
+template <typename S_, typename T, int V, bool CHAR>
+void launch_shape(const SolveParams<S_> &p, dim3 blocks, hipStream_t s) {
     constexpr Shape sh = Variants<T>::shape[V];
     if (p.gx > 0)
-        hipLaunchKernelGGL((solve_kernel<T, sh.threads, sh.waves, true>), blocks, dim3(sh.threads), 0,
-                           s, p);
+        hipLaunchKernelGGL((solve_kernel<S_, T, sh.threads, sh.waves, true, CHAR>), blocks,
+                           dim3(sh.threads), 0, s, p);
     else
-        hipLaunchKernelGGL((solve_kernel<T, sh.threads, sh.waves, false>), blocks, dim3(sh.threads), 0,
-                           s, p);
+        hipLaunchKernelGGL((solve_kernel<S_, T, sh.threads, sh.waves, false, CHAR>), blocks,
+                           dim3(sh.threads), 0, s, p);
+}
+template <typename S_, typename T, int V>
+void launch_variant(const SolveParams<S_> &p, dim3 blocks, hipStream_t s) {
+    if (p.char_limiting)
+        launch_shape<S_, T, V, true>(p, blocks, s);
+    else
+        launch_shape<S_, T, V, false>(p, blocks, s);
 }
 }  // namespace
 
-// variant < 0 selects the default; grid <= 0 launches one work-group per group,
-// grid > 0 a persistent grid that strides over the groups.
-template <typename T>
-hipError_t launch_solve(const SolveParams<T> &p, int variant, int64_t grid, hipStream_t s) {
+// Storage type S_, arithmetic type T (float or S_).  variant < 0 selects the
+// default; grid <= 0 launches one work-group per group, grid > 0 a persistent
+// grid that strides over the groups.
+template <typename S_, typename T>
+hipError_t launch_solve(const SolveParams<S_> &p, int variant, int64_t grid, hipStream_t s) {
     if (p.n_groups <= 0) return hipSuccess;
     const int64_t max_grid = int64_t(1) << 30;
     int64_t g = grid > 0 ? (grid < p.n_groups ? grid : p.n_groups) : p.n_groups;
     if (g > max_grid) g = max_grid;
     const dim3 blocks = dim3(unsigned(g));
     switch (variant < 0 ? 0 : variant) {
-        case 0: launch_variant<T, 0>(p, blocks, s); break;
-        case 1: launch_variant<T, 1>(p, blocks, s); break;
+        case 0: launch_variant<S_, T, 0>(p, blocks, s); break;
+        case 1: launch_variant<S_, T, 1>(p, blocks, s); break;
         case 2:
             if constexpr (Variants<T>::count > 2) {
-                launch_variant<T, 2>(p, blocks, s);
+                launch_variant<S_, T, 2>(p, blocks, s);
                 break;
             }
             return hipErrorInvalidValue;
@@ -730,7 +791,8 @@ template int solve_variant_count<float>();
 template int solve_variant_count<double>();
 template int solve_variant_shape<float>(int, int *, int *);
 template int solve_variant_shape<double>(int, int *, int *);
-template hipError_t launch_solve<float>(const SolveParams<float> &, int, int64_t, hipStream_t);
-template hipError_t launch_solve<double>(const SolveParams<double> &, int, int64_t, hipStream_t);
+template hipError_t launch_solve<float, float>(const SolveParams<float> &, int, int64_t, hipStream_t);
+template hipError_t launch_solve<double, double>(const SolveParams<double> &, int, int64_t, hipStream_t);
+template hipError_t launch_solve<double, float>(const SolveParams<double> &, int, int64_t, hipStream_t);
 
 }  // namespace gamer

@@ -45,6 +45,24 @@ def _f32(dtype):
     raise TypeError(f"unsupported dtype {dtype}")
 
 
+def _opts(theta, variant, grid, limiting):
+    if theta is None and variant is None and grid is None and limiting is None:
+        return None
+    lim = {None: 0, "primitive": 0, "characteristic": 1}.get(limiting, limiting)
+    return _native.GamerOpts(float(theta or 0.0), int(variant or 0), int(grid or 0), int(lim), 0)
+
+
+def _solver_fn(name, dtype, compute):
+    """Entry point for storage dtype and arithmetic dtype `compute` (None: the
+    storage dtype; float32 with float64 storage: the mixed-precision path)."""
+    f32 = _f32(dtype)
+    if compute is None or compute == dtype:
+        return getattr(_native.lib(), name + ("_f32" if f32 else ""))
+    if dtype == torch.float64 and compute == torch.float32:
+        return getattr(_native.lib(), name + "_mixed")
+    raise TypeError(f"no {name} path storing {dtype} and computing in {compute}")
+
+
 def hydro_solve(groups_in, dt, dh, gamma, out=None, fluxes_out=None):
     """One MUSCL-Hancock + Roe step of every padded group (same dt, dh)."""
     f32 = _f32(groups_in.dtype)
@@ -62,11 +80,14 @@ def hydro_solve(groups_in, dt, dh, gamma, out=None, fluxes_out=None):
 
 
 def hydro_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxes_out=None,
-                        group_stats=None, theta=None, variant=None, grid=None):
+                        group_stats=None, theta=None, variant=None, grid=None, limiting=None,
+                        compute=None):
     """One launch over groups of uneven level; dt and dh read on the device.
-    `variant` / `grid` select a compiled solver variant and a persistent grid
-    (see gamer_opts); None keeps the defaults."""
-    f32 = _f32(groups_in.dtype)
+    `variant` / `grid` select a compiled solver variant and a persistent grid,
+    `limiting` "primitive" or "characteristic" (see gamer_opts); None keeps the
+    defaults.  `compute=torch.float32` with float64 arrays selects the FP64-state,
+    FP32-arithmetic path."""
+    fn = _solver_fn("gamer_hydro_solve_batched", groups_in.dtype, compute)
     _need(groups_in, (NV, NP, NP, NP), groups_in.dtype, "groups_in")
     n = groups_in.shape[0]
     if out is None:
@@ -83,12 +104,8 @@ def hydro_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxe
         if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 1:
             raise ValueError(f"{nm} must be a 1-D GPU float64 tensor")
     n_levels = dt_dev.numel()
-    opts = None
-    if theta is not None or variant is not None or grid is not None:
-        opts = _native.GamerOpts(float(theta or 0.0), int(variant or 0), int(grid or 0))
+    opts = _opts(theta, variant, grid, limiting)
     _stream()
-    fn = (_native.lib().gamer_hydro_solve_batched_f32 if f32
-          else _native.lib().gamer_hydro_solve_batched)
     _native.check(fn(_ptr(groups_in), n, _ptr(level), _ptr(dt_dev), _ptr(dh_dev), n_levels,
                      float(gamma), _ptr(fluxes_out), _ptr(out), _ptr(group_stats),
                      ctypes.byref(opts) if opts is not None else None))
@@ -96,10 +113,12 @@ def hydro_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxe
 
 
 def hydro_solve_periodic(state, gx, gy, gz, dt_dev, dh_dev, gamma, out=None, fluxes_out=None,
-                         group_stats=None, theta=None, variant=None, grid=None):
+                         group_stats=None, theta=None, variant=None, grid=None, limiting=None,
+                         compute=None):
     """One step of a uniform periodic grid; ghost cells are read from the
-    neighbouring groups in place (no padded copy).  `out` must not be `state`."""
-    f32 = _f32(state.dtype)
+    neighbouring groups in place (no padded copy).  `out` must not be `state`.
+    Options as in hydro_solve_batched."""
+    fn = _solver_fn("gamer_hydro_solve_periodic", state.dtype, compute)
     _need(state, (NV, NI, NI, NI), state.dtype, "state")
     n = state.shape[0]
     if n != gx * gy * gz:
@@ -114,12 +133,8 @@ def hydro_solve_periodic(state, gx, gy, gz, dt_dev, dh_dev, gamma, out=None, flu
     for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
         if t.dtype != torch.float64 or not t.is_cuda or t.numel() < 1:
             raise ValueError(f"{nm} must be a GPU float64 tensor")
-    opts = None
-    if theta is not None or variant is not None or grid is not None:
-        opts = _native.GamerOpts(float(theta or 0.0), int(variant or 0), int(grid or 0))
+    opts = _opts(theta, variant, grid, limiting)
     _stream()
-    fn = (_native.lib().gamer_hydro_solve_periodic_f32 if f32
-          else _native.lib().gamer_hydro_solve_periodic)
     _native.check(fn(_ptr(state), int(gx), int(gy), int(gz), _ptr(dt_dev), _ptr(dh_dev), float(gamma),
                      _ptr(fluxes_out), _ptr(out), _ptr(group_stats),
                      ctypes.byref(opts) if opts is not None else None))

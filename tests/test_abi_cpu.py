@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 27
+    assert len(names) == 29
     for n in names:
         assert hasattr(lib, n), n
         assert n in _native.SIGNATURES, n
@@ -37,9 +37,10 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_opts_struct_layout():
-    # gamer_opts: double theta, int32 variant, int32 grid
-    assert ctypes.sizeof(_native.GamerOpts) == 16
+    # gamer_opts: double theta, int32 variant, int32 grid, int32 limiting, int32 reserved
+    assert ctypes.sizeof(_native.GamerOpts) == 24
     assert _native.GamerOpts.variant.offset == 8 and _native.GamerOpts.grid.offset == 12
+    assert _native.GamerOpts.limiting.offset == 16 and _native.GamerOpts.reserved.offset == 20
 
 
 def test_solver_variants(lib):
@@ -100,6 +101,27 @@ def test_batched_argument_errors(lib):
     assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
     bad = _native.GamerOpts(1.5, 0, -4)
     assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+
+
+def test_limiting_and_mixed_argument_errors(lib):
+    E = _native.GAMER_EINVAL
+    Q = ctypes.c_void_p(0x2000)
+    for lim, res in ((2, 0), (-1, 0), (0, 3)):
+        bad = _native.GamerOpts(1.5, 0, 0, lim, res)
+        assert lib.gamer_hydro_solve_batched(P, 4, None, P, P, 1, 1.4, None, Q, None,
+                                             ctypes.byref(bad)) == E
+        assert lib.gamer_hydro_solve_periodic_mixed(P, 2, 2, 2, P, P, 1.4, None, Q, None,
+                                                    ctypes.byref(bad)) == E
+    f = lib.gamer_hydro_solve_batched_mixed
+    assert f(P, 4, None, None, P, 1, 1.4, None, Q, None, None) == E  # no dt_dev
+    assert f(P, 4, None, P, None, 1, 1.4, None, Q, None, None) == E  # no dh_dev
+    assert f(P, 4, None, P, P, 0, 1.4, None, Q, None, None) == E
+    assert f(None, 4, None, P, P, 1, 1.4, None, Q, None, None) == E
+    bad = _native.GamerOpts(1.5, lib.gamer_solver_variants(1), 0, 0, 0)  # float variants index
+    assert f(P, 4, None, P, P, 1, 1.4, None, Q, None, ctypes.byref(bad)) == E
+    g = lib.gamer_hydro_solve_periodic_mixed
+    assert g(P, 0, 2, 2, P, P, 1.4, None, Q, None, None) == E
+    assert g(P, 2, 2, 2, P, P, 1.4, None, P, None, None) == E
 
 
 def test_periodic_argument_errors(lib):
