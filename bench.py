@@ -299,6 +299,51 @@ def bench_amr(tag, state, g, dh, steps):
     return out
 
 
+RTVD_VALUES_PER_GROUP = 16 ** 3 + 2 * (16 * 22 * 22) + 2 * (16 * 16 * 22) + 16 ** 3
+
+
+def bench_rtvd(tag, state, g, dh, steps, warmup):
+    """The relaxing TVD scheme on the same periodic grid: one step = three
+    sweep launches (ghost cells read in place by the first), alternating the
+    sweep order.  Algorithmic bytes per group: read the state once, write and
+    read the two intermediate blocks, write the result."""
+    import torch
+    from paper_1007_3818_amd import hydro
+
+    n = g ** 3
+    dev = state.device
+    dh_dev = torch.full((1,), dh, dtype=torch.float64, device=dev)
+    # the same CFL time step as the MUSCL-Hancock step (0.5 dh / max(|u|+|v|+|w|+3c)),
+    # within the split scheme's per-direction limit
+    stats = torch.empty((n, 8), dtype=torch.float64, device=dev)
+    dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
+    hydro.group_stats(state, GAMMA, out=stats)
+    hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev)
+    work = hydro.rtvd_workspace(n, state.dtype, dev)
+    cur, nxt = state.clone(), torch.empty_like(state)
+    for k in range(warmup):
+        hydro.rtvd_solve_periodic(cur, g, g, g, dt_dev, dh_dev, GAMMA, k % 2, out=nxt, work=work)
+        cur, nxt = nxt, cur
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for k in range(steps):
+        hydro.rtvd_solve_periodic(cur, g, g, g, dt_dev, dh_dev, GAMMA, k % 2, out=nxt, work=work)
+        cur, nxt = nxt, cur
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    cells = n * CELLS
+    if not bool(torch.isfinite(cur).all()):
+        return {"error": "non-finite values after the timed steps", "ms_per_step": ms}
+    b = RTVD_VALUES_PER_GROUP * 5 * state.element_size() * n
+    return {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+            "algorithmic_bytes_per_cell": b / cells, "hbm_GBps": b / (ms * 1e-3) / 1e9,
+            "hbm_frac": b / (ms * 1e-3) / HBM_PEAK,
+            "step": "three sweeps (x,y,z / z,y,x alternating), ghost cells read in place, CFL dt of "
+                    "the initial state"}
+
+
 def cpu_baseline(padded64_host, dh, dt):
     """The FP64 oracle on host cores: all groups of the workload, one step, with
     as many threads as the host offers (capped at 16)."""
@@ -336,6 +381,7 @@ def main():
                     help="2: smooth modes 256^3 (the metric's configuration); 5: 1024^3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-amr", action="store_true", help="skip the coarse/fine kernel timings")
+    ap.add_argument("--no-rtvd", action="store_true", help="skip the relaxing TVD timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--variant", type=int, default=None,
@@ -370,6 +416,11 @@ def main():
         res["f32"] = bench_dtype("f32", state.float(), g, dh, args.steps, args.warmup, shape)
     if args.dtype in ("f64", "both"):
         res["f64"] = bench_dtype("f64", state, g, dh, args.steps, args.warmup, shape)
+    if not args.no_rtvd:
+        for tag in list(res):
+            progress(f"{tag}: relaxing TVD scheme")
+            st = state.float() if tag == "f32" else state
+            res[tag]["rtvd"] = bench_rtvd(tag, st, g, dh, args.steps, args.warmup)
     if not args.no_amr:
         for tag in list(res):
             progress(f"{tag}: coarse/fine correction and restriction kernels")

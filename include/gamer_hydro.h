@@ -49,6 +49,7 @@
 #ifndef GAMER_HYDRO_H
 #define GAMER_HYDRO_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -232,6 +233,47 @@ int gamer_conserved_sums_f32(const float *groups, int64_t n_groups, double dh,
  * gx*gy*gz*100 > INT32_MAX (about 21 million groups), NULL or misaligned arrays. */
 int gamer_pack_periodic(const double *state, int gx, int gy, int gz, double *padded);
 int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *padded);
+
+/* ---- the relaxing TVD scheme (the solver the paper compares with) --------
+ * The paper's Sec. 2 compares MUSCL-Hancock with the scheme GAMER used
+ * before: the second-order relaxing total-variation-diminishing scheme of
+ * Trac & Pen (2003), made three-dimensional by dimensional splitting, whose
+ * seven-point stencil needs three ghost cells per side.  One step sweeps x,
+ * y, z (order 0) or z, y, x (order 1; alternate the two between steps).  Per
+ * sweep along d, with the freezing speed c = |v_d| + c_s and w = F_d(u)/c of
+ * each cell, the right- and left-moving fluxes fr = c (u + w), fl = c (u - w)
+ * give first-order face fluxes (fr_i - fl_{i+1})/2 for a half step of dt/2,
+ * then, from the half-step state, second-order face fluxes with van Leer's
+ * limiter on each moving part for the full step of dt:
+ *   R = fr_i + VL((fr_i - fr_{i-1})/2, (fr_{i+1} - fr_i)/2),
+ *   L = fl_{i+1} + VL((fl_i - fl_{i+1})/2, (fl_{i+1} - fl_{i+2})/2),
+ *   F = (R - L)/2,   VL(a, b) = 2ab/(a+b) if ab > 0 else 0.
+ * Input: padded groups [n][5][22][22][22] (cells -3..18 per axis) or, for the
+ * periodic entry points, the state of a periodic grid of groups as in
+ * gamer_hydro_solve_periodic.  Output: [n][5][16][16][16]; it must not alias
+ * the input.  dt and dh are read on the device per level as in the batched
+ * MUSCL-Hancock step (level may be NULL; the periodic entry points use
+ * dt_dev[0], dh_dev[0]).  The FP32 variants compute in float and form each
+ * sweep's update u - dt/dx (F_{i+1/2} - F_{i-1/2}) in double, rounding once.
+ * work: device workspace of gamer_rtvd_workspace_bytes(n, f32) bytes, 16-byte
+ * aligned, owned by the caller (nothing is allocated inside).  States with
+ * rho <= 0 or p <= 0 are not caught (the scheme has no fallback).
+ * Errors: GAMER_EINVAL for bad sizes or order, NULL or aliased arrays, a
+ * missing or short workspace. */
+size_t gamer_rtvd_workspace_bytes(int64_t n_groups, int f32);
+int gamer_rtvd_solve_batched(const double *groups_in, int64_t n_groups, const int8_t *level,
+                             const double *dt_dev, const double *dh_dev, int n_levels, double gamma,
+                             int order, void *work, size_t work_bytes, double *groups_out);
+int gamer_rtvd_solve_batched_f32(const float *groups_in, int64_t n_groups, const int8_t *level,
+                                 const double *dt_dev, const double *dh_dev, int n_levels,
+                                 double gamma, int order, void *work, size_t work_bytes,
+                                 float *groups_out);
+int gamer_rtvd_solve_periodic(const double *state, int gx, int gy, int gz, const double *dt_dev,
+                              const double *dh_dev, double gamma, int order, void *work,
+                              size_t work_bytes, double *state_out);
+int gamer_rtvd_solve_periodic_f32(const float *state, int gx, int gy, int gz, const double *dt_dev,
+                                  const double *dh_dev, double gamma, int order, void *work,
+                                  size_t work_bytes, float *state_out);
 
 /* ---- two refinement levels: flux correction and restriction -------------
  * The steps that follow the solver when a coarse level and a fine level at

@@ -29,7 +29,7 @@ def _lib():
     global _LIB
     if _LIB is None:
         if not os.path.exists(_build.LIB) or (
-                os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
+                os.path.getmtime(_build.LIB) < max(os.path.getmtime(f) for f in _build.SRCS)):
             _build.build()
         lib = ctypes.CDLL(_build.LIB)
         sig = {
@@ -55,6 +55,9 @@ def _lib():
             "gamer_oracle_cfl_dt": (_D, [_PD, _I64, _D, _D, _D]),
             "gamer_oracle_conserved_sums": (None, [_PD, _I64, _D, _PD]),
             "gamer_oracle_pack_periodic": (None, [_PD, ctypes.c_int, ctypes.c_int, ctypes.c_int, _PD]),
+            "gamer_oracle_vanleer": (_D, [_D, _D]),
+            "gamer_oracle_rtvd_pencil": (ctypes.c_longlong, [_PD, ctypes.c_int, ctypes.c_int, _D, _D, _PD]),
+            "gamer_oracle_rtvd_solve": (ctypes.c_int, [_PD, _I64, _D, _D, _D, ctypes.c_int, _PD, _PLL]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -257,3 +260,58 @@ def step_periodic(state, gx, gy, gz, dt, dh, gamma, theta=THETA, limiting="primi
     out, _, counts = hydro_solve(pack_periodic(state, gx, gy, gz), dt, dh, gamma, theta,
                                  limiting=limiting)
     return out, counts
+
+
+# --- relaxing TVD (gamer_rtvd.c) ----------------------------------------------
+
+RG = 3  # ghost cells per side of the relaxing TVD scheme's seven-point stencil
+
+
+def vanleer(a, b):
+    return _lib().gamer_oracle_vanleer(float(a), float(b))
+
+
+def rtvd_pencil(u, d, dtdx, gamma):
+    """One relaxing-TVD update of a pencil u (n, 5) along direction d:
+    returns (cells 3 .. n-4 as (n-6, 5), bad-cell count)."""
+    u = _f64(u)
+    n = u.shape[0]
+    out = np.empty((n - 6, 5))
+    bad = _lib().gamer_oracle_rtvd_pencil(_p(u), n, int(d), float(dtdx), float(gamma), _p(out))
+    return out, int(bad)
+
+
+def rtvd_solve(groups_in, dt, dh, gamma, order=0):
+    """One relaxing-TVD step of padded groups (n, 5, 22, 22, 22) -> (n, 5, 16, 16, 16);
+    order 0 sweeps x, y, z, order 1 z, y, x.  Returns (out, bad-cell count)."""
+    g = _f64(groups_in)
+    assert g.ndim == 5 and g.shape[1:] == (5, 22, 22, 22), g.shape
+    n = g.shape[0]
+    out = np.empty((n, 5, 16, 16, 16))
+    bad = ctypes.c_longlong(0)
+    rc = _lib().gamer_oracle_rtvd_solve(_p(g), n, dt, dh, gamma, int(order), _p(out), ctypes.byref(bad))
+    if rc != 0:
+        raise ValueError("oracle rtvd_solve rejected its arguments")
+    return out, int(bad.value)
+
+
+def pack_periodic_rtvd(state, gx, gy, gz):
+    """Padded groups with three ghost cells per side, (G, 5, 22, 22, 22), from
+    a periodic grid of groups (G, 5, 16, 16, 16): each padded cell is the cell
+    at its wrapped global position (brute force over the global array)."""
+    s = _f64(state)
+    G = s.reshape(gz, gy, gx, 5, 16, 16, 16).transpose(3, 0, 4, 1, 5, 2, 6).reshape(
+        5, gz * 16, gy * 16, gx * 16)
+    out = np.empty((gx * gy * gz, 5, 22, 22, 22))
+    for g in range(gx * gy * gz):
+        bx, by, bz = g % gx, (g // gx) % gy, g // (gx * gy)
+        ix = np.arange(16 * bx - RG, 16 * bx + 16 + RG) % G.shape[3]
+        iy = np.arange(16 * by - RG, 16 * by + 16 + RG) % G.shape[2]
+        iz = np.arange(16 * bz - RG, 16 * bz + 16 + RG) % G.shape[1]
+        out[g] = G[:, iz][:, :, iy][:, :, :, ix]
+    return out
+
+
+def rtvd_step_periodic(state, gx, gy, gz, dt, dh, gamma, order=0):
+    out, bad = rtvd_solve(pack_periodic_rtvd(state, gx, gy, gz), dt, dh, gamma, order)
+    return out, bad

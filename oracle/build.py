@@ -9,13 +9,14 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "gamer_oracle.c")
+SRCS = [SRC, os.path.join(HERE, "gamer_rtvd.c")]
 LIB = os.path.join(HERE, "libgamer_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, *SRCS, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -276,6 +276,44 @@ int restrict_common(const T *fine, const int64_t *parent, int64_t n_fine, T *coa
                      "restrict launch");
 }
 
+template <typename T>
+int rtvd_common(const T *in, int gx, int gy, int gz, int64_t n, const int8_t *level,
+                const double *dt_dev, const double *dh_dev, int n_levels, double gamma, int order,
+                void *work, size_t work_bytes, T *out) {
+    g_err[0] = 0;
+    if (n < 0) return fail(GAMER_EINVAL, "n_groups < 0");
+    if (!(isfinite(gamma) && gamma > 1.0)) return fail(GAMER_EINVAL, "gamma must be > 1");
+    if (order != 0 && order != 1) return fail(GAMER_EINVAL, "order must be 0 (x, y, z) or 1 (z, y, x)");
+    if (n == 0) return GAMER_OK;
+    if (!in || !out || !dt_dev || !dh_dev) return fail(GAMER_EINVAL, "NULL array argument");
+    if (n_levels < 1 || n_levels > GAMER_MAX_LEVELS)
+        return fail(GAMER_EINVAL, "n_levels must lie in [1, %d]", GAMER_MAX_LEVELS);
+    if (static_cast<const void *>(in) == static_cast<const void *>(out))
+        return fail(GAMER_EINVAL, "input and output must be different arrays");
+    const size_t need = rtvd_workspace_elems<T>(n) * sizeof(T);
+    if (!work || work_bytes < need)
+        return fail(GAMER_EINVAL, "workspace of %zu bytes required", need);
+    if (reinterpret_cast<uintptr_t>(work) % 16) return fail(GAMER_EINVAL, "workspace must be 16-byte aligned");
+    if (n * 31 > INT32_MAX) return fail(GAMER_EINVAL, "too many groups for one launch");
+    return check_hip(launch_rtvd<T>(in, gx, gy, gz, n, level, dt_dev, dh_dev, gamma, order,
+                                    static_cast<T *>(work), out, g_stream),
+                     "relaxing TVD launch");
+}
+
+template <typename T>
+int rtvd_periodic_common(const T *state, int gx, int gy, int gz, const double *dt_dev,
+                         const double *dh_dev, double gamma, int order, void *work, size_t work_bytes,
+                         T *out) {
+    g_err[0] = 0;
+    if (gx < 1 || gy < 1 || gz < 1) return fail(GAMER_EINVAL, "gx, gy, gz must be >= 1");
+    const int64_t n = int64_t(gx) * gy * gz;
+    if (int64_t(gx) * NI > (1 << 28) || int64_t(gy) * NI > (1 << 28) || int64_t(gz) * NI > (1 << 28) ||
+        n > INT32_MAX)
+        return fail(GAMER_EINVAL, "grid too large: gx, gy, gz <= 2^24 and gx*gy*gz < 2^31 required");
+    return rtvd_common<T>(state, gx, gy, gz, n, nullptr, dt_dev, dh_dev, 1, gamma, order, work,
+                          work_bytes, out);
+}
+
 }  // namespace
 
 extern "C" {
@@ -415,6 +453,41 @@ int gamer_pack_periodic(const double *state, int gx, int gy, int gz, double *pad
 
 int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *padded) {
     return pack_common<float>(state, gx, gy, gz, padded);
+}
+
+size_t gamer_rtvd_workspace_bytes(int64_t n_groups, int f32) {
+    if (n_groups <= 0) return 0;
+    return f32 ? rtvd_workspace_elems<float>(n_groups) * sizeof(float)
+               : rtvd_workspace_elems<double>(n_groups) * sizeof(double);
+}
+
+int gamer_rtvd_solve_batched(const double *groups_in, int64_t n_groups, const int8_t *level,
+                             const double *dt_dev, const double *dh_dev, int n_levels, double gamma,
+                             int order, void *work, size_t work_bytes, double *groups_out) {
+    return rtvd_common<double>(groups_in, 0, 0, 0, n_groups, level, dt_dev, dh_dev, n_levels, gamma,
+                               order, work, work_bytes, groups_out);
+}
+
+int gamer_rtvd_solve_batched_f32(const float *groups_in, int64_t n_groups, const int8_t *level,
+                                 const double *dt_dev, const double *dh_dev, int n_levels,
+                                 double gamma, int order, void *work, size_t work_bytes,
+                                 float *groups_out) {
+    return rtvd_common<float>(groups_in, 0, 0, 0, n_groups, level, dt_dev, dh_dev, n_levels, gamma,
+                              order, work, work_bytes, groups_out);
+}
+
+int gamer_rtvd_solve_periodic(const double *state, int gx, int gy, int gz, const double *dt_dev,
+                              const double *dh_dev, double gamma, int order, void *work,
+                              size_t work_bytes, double *state_out) {
+    return rtvd_periodic_common<double>(state, gx, gy, gz, dt_dev, dh_dev, gamma, order, work,
+                                        work_bytes, state_out);
+}
+
+int gamer_rtvd_solve_periodic_f32(const float *state, int gx, int gy, int gz, const double *dt_dev,
+                                  const double *dh_dev, double gamma, int order, void *work,
+                                  size_t work_bytes, float *state_out) {
+    return rtvd_periodic_common<float>(state, gx, gy, gz, dt_dev, dh_dev, gamma, order, work,
+                                       work_bytes, state_out);
 }
 
 int gamer_flux_accumulate(const double *fluxes, int64_t n_groups, const double *dt_dev, int reset,

@@ -64,6 +64,15 @@ hipError_t launch_reduce(const double *stats, int64_t n, const int8_t *level, co
                          double dh, int n_levels, double cfl, double *dt_out, double *totals_out,
                          hipStream_t s);
 
+// relaxing TVD (rtvd.hip): elements of workspace for n groups; one step of
+// padded groups [n][5][22][22][22] (gx == 0) or of a periodic grid of groups
+template <typename T>
+size_t rtvd_workspace_elems(int64_t n_groups);
+template <typename T>
+hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int8_t *level,
+                       const double *dt_dev, const double *dh_dev, double gamma, int order, T *work,
+                       T *out, hipStream_t s);
+
 // two refinement levels (amr.hip)
 template <typename T>
 hipError_t launch_flux_accumulate(const T *fluxes, int64_t n_groups, const double *dt_dev, int reset,

@@ -1,0 +1,256 @@
+// rtvd.hip -- the relaxing TVD scheme (the solver the paper compares
+// MUSCL-Hancock with): three dimensionally split sweeps per step, one launch
+// per sweep.  A work-group takes 16 pencils of one group along the sweep
+// direction, stages them in LDS, and advances each pencil by the relaxing
+// scheme's half step and full step; the block shrinks by three cells per side
+// along the sweep direction only, so the three sweeps go 22^3 -> 16 x 22 x 22
+// -> 16 x 16 x 22 -> 16^3 (x, y, z order) through two workspace arrays.
+#include "device_math.h"
+#include "internal.h"
+
+namespace gamer {
+namespace {
+
+constexpr int RP = 22;      // padded cells per axis (three ghost cells per side)
+constexpr int RG = 3;
+constexpr int PEN = 16;     // pencils per work-group
+constexpr int PSTR = PEN + 1;  // LDS row stride (bank-conflict padding)
+
+template <typename T>
+struct SweepArgs {
+    const T *in;      // block [n][5][ez][ey][ex], or the periodic state (gx > 0)
+    int gx, gy, gz;   // > 0: the first sweep reads a periodic grid of groups
+    int ex, ey, ez;   // input block extents
+    int d;            // sweep axis
+    T *out;           // [n][5][..] with extent e[d] - 6 along d
+    const int8_t *level;
+    const double *dt_dev, *dh_dev;
+    double gamma;
+    int64_t n_groups;
+    int tiles;        // work-groups per group
+};
+
+template <typename T>
+struct RtvdLds {
+    T u[NV][RP][PSTR];   // the pencils' input
+    T fr[NV][RP][PSTR];  // c (u + w), then from the half-step state
+    T fl[NV][RP][PSTR];  // c (u - w), likewise
+};
+
+// freezing speed c = |v_d| + c_s and the right/left-moving fluxes
+// fr = c (u + w), fl = c (u - w) with w = F_d(u) / c
+template <typename T>
+__device__ __forceinline__ void relax(const T u[NV], int d, T g, T gm1, T fr[NV], T fl[NV]) {
+    const T ir = rcp(u[0]);
+    const T vx = u[1] * ir, vy = u[2] * ir, vz = u[3] * ir;
+    const T vd = d == 0 ? vx : (d == 1 ? vy : vz);
+    const T p = gm1 * (u[4] - T(0.5) * (u[1] * vx + u[2] * vy + u[3] * vz));
+    const T c = fabs(vd) + sqrt_(g * p * ir);
+    const T ic = rcp(c);
+    T F[NV];
+    F[0] = u[1 + d];
+    F[1] = u[1] * vd;
+    F[2] = u[2] * vd;
+    F[3] = u[3] * vd;
+    F[1 + d] += p;
+    F[4] = (u[4] + p) * vd;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const T w = F[v] * ic;
+        fr[v] = c * (u[v] + w);
+        fl[v] = c * (u[v] - w);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T vanleer(T a, T b) {
+    const T ab = a * b;
+    return ab > T(0) ? T(2) * ab * rcp(a + b) : T(0);
+}
+
+template <typename T, bool PERIODIC>
+__global__ __launch_bounds__(256) void rtvd_sweep_kernel(SweepArgs<T> P) {
+    __shared__ RtvdLds<T> S;
+    const int t = threadIdx.x;
+    const int64_t g = blockIdx.x / P.tiles;
+    const int tile = blockIdx.x - int(g * P.tiles);
+    if (g >= P.n_groups) return;
+    const int d = P.d;
+    const int e[3] = {P.ex, P.ey, P.ez};
+    int eo[3] = {P.ex, P.ey, P.ez};
+    eo[d] -= 2 * RG;
+    const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;  // transverse axes, a varies fastest
+    const int npen = e[a] * e[b];
+    const int64_t vin = int64_t(e[0]) * e[1] * e[2], vout = int64_t(eo[0]) * eo[1] * eo[2];
+    // thread <-> (pencil q, position l): positions fastest for x sweeps
+    // (contiguous pencils), pencils fastest otherwise
+    const int q = d == 0 ? (t >> 4) : (t & 15);
+    const int l = d == 0 ? (t & 15) : (t >> 4);
+    const int p = tile * PEN + q;  // pencil index within the group
+    const bool live = p < npen;
+    int idx[3];
+    idx[a] = live ? p % e[a] : 0;
+    idx[b] = live ? p / e[a] : 0;
+
+    int lev = P.level ? int(P.level[g]) : 0;
+    const double dt = P.dt_dev[lev], dh = P.dh_dev[lev];
+    const double dtdx = dt / dh;
+    const T g_ = T(P.gamma), gm1 = T(P.gamma - 1.0);
+
+    // ---- load the 16 pencils (positions 0..21) ----
+    for (int s = l; s < RP; s += PEN) {
+        if (!live) break;
+        idx[d] = s;
+        const T *src;
+        if constexpr (PERIODIC) {
+            const int bx = int(g % P.gx), by = int((g / P.gx) % P.gy), bz = int(g / (int64_t(P.gx) * P.gy));
+            const int NX = P.gx * NI, NY = P.gy * NI, NZ = P.gz * NI;
+            int X = bx * NI + idx[0] - RG, Y = by * NI + idx[1] - RG, Z = bz * NI + idx[2] - RG;
+            X = X < 0 ? X + NX : (X >= NX ? X - NX : X);
+            Y = Y < 0 ? Y + NY : (Y >= NY ? Y - NY : Y);
+            Z = Z < 0 ? Z + NZ : (Z >= NZ ? Z - NZ : Z);
+            const int64_t grp = X / NI + int64_t(P.gx) * (Y / NI + int64_t(P.gy) * (Z / NI));
+            src = P.in + grp * GOUT + ((Z % NI) * NI + (Y % NI)) * NI + (X % NI);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) S.u[v][s][q] = src[v * (NI * NI * NI)];
+        } else {
+            src = P.in + g * NV * vin + (int64_t(idx[2]) * e[1] + idx[1]) * e[0] + idx[0];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) S.u[v][s][q] = src[v * vin];
+        }
+    }
+    __syncthreads();
+
+    // ---- half step: first-order relaxed fluxes ----
+    for (int s = l; s < RP; s += PEN) {
+        T u[NV], fr[NV], fl[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = live ? S.u[v][s][q] : T(1);
+        if (!live) u[4] = T(2);
+        relax(u, d, g_, gm1, fr, fl);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            S.fr[v][s][q] = fr[v];
+            S.fl[v][s][q] = fl[v];
+        }
+    }
+    __syncthreads();
+    // half-step state of positions 1..20, two per lane at most
+    T h[2][NV];
+    const T hdt = T(0.5 * dtdx);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int s = 1 + l + r * PEN;
+        if (s <= RP - 2) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const T Fp = T(0.5) * (S.fr[v][s][q] - S.fl[v][s + 1][q]);
+                const T Fm = T(0.5) * (S.fr[v][s - 1][q] - S.fl[v][s][q]);
+                h[r][v] = S.u[v][s][q] - hdt * (Fp - Fm);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int s = 1 + l + r * PEN;
+        if (s <= RP - 2) {
+            T fr[NV], fl[NV];
+            if (!live) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) h[r][v] = T(1);
+                h[r][4] = T(2);
+            }
+            relax(h[r], d, g_, gm1, fr, fl);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                S.fr[v][s][q] = fr[v];
+                S.fl[v][s][q] = fl[v];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- full step: second-order fluxes on both faces of cell i = l + 3 ----
+    if (!live) return;
+    const int i = l + RG;
+    idx[d] = l;
+    T *dst = P.out + g * NV * vout + (int64_t(idx[2]) * eo[1] + idx[1]) * eo[0] + idx[0];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        T F[2];
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            const int c0 = i - 1 + f;  // face c0 + 1/2
+            const T r0 = S.fr[v][c0 - 1][q], r1 = S.fr[v][c0][q], r2 = S.fr[v][c0 + 1][q];
+            const T l1 = S.fl[v][c0][q], l2 = S.fl[v][c0 + 1][q], l3 = S.fl[v][c0 + 2][q];
+            const T R = r1 + vanleer(T(0.5) * (r1 - r0), T(0.5) * (r2 - r1));
+            const T L = l2 + vanleer(T(0.5) * (l1 - l2), T(0.5) * (l2 - l3));
+            F[f] = T(0.5) * (R - L);
+        }
+        const double o = double(S.u[v][i][q]) - dtdx * (double(F[1]) - double(F[0]));
+        dst[v * vout] = T(o);
+    }
+}
+
+}  // namespace
+
+template <typename T>
+size_t rtvd_workspace_elems(int64_t n_groups) {
+    // two intermediate blocks: 16 x 22 x 22 and 16 x 16 x 22 cells per group
+    return size_t(n_groups) * NV * (NI * RP * RP + NI * NI * RP);
+}
+
+template <typename T>
+hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int8_t *level,
+                       const double *dt_dev, const double *dh_dev, double gamma, int order, T *work,
+                       T *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int dirs[2][3] = {{0, 1, 2}, {2, 1, 0}};
+    T *b1 = work;
+    T *b2 = work + size_t(n) * NV * NI * RP * RP;
+    int e[3] = {RP, RP, RP};
+    const T *src = in;
+    for (int k = 0; k < 3; ++k) {
+        const int d = dirs[order][k];
+        SweepArgs<T> P;
+        P.in = src;
+        P.gx = k == 0 ? gx : 0;
+        P.gy = gy;
+        P.gz = gz;
+        P.ex = e[0];
+        P.ey = e[1];
+        P.ez = e[2];
+        P.d = d;
+        P.out = k == 0 ? b1 : (k == 1 ? b2 : out);
+        P.level = level;
+        P.dt_dev = dt_dev;
+        P.dh_dev = dh_dev;
+        P.gamma = gamma;
+        P.n_groups = n;
+        const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
+        P.tiles = (e[ta] * e[tb] + PEN - 1) / PEN;
+        const int64_t blocks = n * P.tiles;
+        if (blocks > int64_t(1) << 31) return hipErrorInvalidValue;
+        if (P.gx > 0)
+            hipLaunchKernelGGL((rtvd_sweep_kernel<T, true>), dim3(unsigned(blocks)), dim3(256), 0, s, P);
+        else
+            hipLaunchKernelGGL((rtvd_sweep_kernel<T, false>), dim3(unsigned(blocks)), dim3(256), 0, s, P);
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+        src = P.out;
+        e[d] -= 2 * RG;
+    }
+    return hipSuccess;
+}
+
+template size_t rtvd_workspace_elems<float>(int64_t);
+template size_t rtvd_workspace_elems<double>(int64_t);
+template hipError_t launch_rtvd<float>(const float *, int, int, int, int64_t, const int8_t *,
+                                       const double *, const double *, double, int, float *, float *,
+                                       hipStream_t);
+template hipError_t launch_rtvd<double>(const double *, int, int, int, int64_t, const int8_t *,
+                                        const double *, const double *, double, int, double *,
+                                        double *, hipStream_t);
+
+}  // namespace gamer

@@ -213,6 +213,68 @@ def pack_periodic(state, gx, gy, gz, out=None):
     return out
 
 
+# ---- the relaxing TVD scheme ----------------------------------------------
+
+RP = 22  # padded cells per axis of the relaxing TVD scheme
+
+
+def rtvd_workspace(n_groups, dtype, device):
+    """A workspace tensor of the size the relaxing-TVD entry points need."""
+    nbytes = _native.lib().gamer_rtvd_workspace_bytes(int(n_groups), int(_f32(dtype)))
+    return torch.empty(max(nbytes, 16), dtype=torch.uint8, device=device)
+
+
+def _work(work, n, dtype, device):
+    if work is None:
+        work = rtvd_workspace(n, dtype, device)
+    if not isinstance(work, torch.Tensor) or not work.is_cuda or not work.is_contiguous():
+        raise ValueError("work must be a contiguous GPU tensor")
+    return work
+
+
+def rtvd_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, order=0, out=None, work=None):
+    """One relaxing-TVD step of padded groups (n, 5, 22, 22, 22)."""
+    f32 = _f32(groups_in.dtype)
+    _need(groups_in, (NV, RP, RP, RP), groups_in.dtype, "groups_in")
+    n = groups_in.shape[0]
+    if out is None:
+        out = torch.empty((n, NV, NI, NI, NI), dtype=groups_in.dtype, device=groups_in.device)
+    _need(out, (NV, NI, NI, NI), groups_in.dtype, "out")
+    if level is not None:
+        if level.dtype != torch.int8 or not level.is_cuda or level.numel() != n:
+            raise ValueError("level must be a GPU int8 tensor with one entry per group")
+    for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
+        if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 1:
+            raise ValueError(f"{nm} must be a 1-D GPU float64 tensor")
+    work = _work(work, n, groups_in.dtype, groups_in.device)
+    _stream()
+    fn = _native.lib().gamer_rtvd_solve_batched_f32 if f32 else _native.lib().gamer_rtvd_solve_batched
+    _native.check(fn(_ptr(groups_in), n, _ptr(level), _ptr(dt_dev), _ptr(dh_dev), dt_dev.numel(),
+                     float(gamma), int(order), _ptr(work), work.numel() * work.element_size(), _ptr(out)))
+    return out
+
+
+def rtvd_solve_periodic(state, gx, gy, gz, dt_dev, dh_dev, gamma, order=0, out=None, work=None):
+    """One relaxing-TVD step of a uniform periodic grid, ghost cells read in place."""
+    f32 = _f32(state.dtype)
+    _need(state, (NV, NI, NI, NI), state.dtype, "state")
+    n = state.shape[0]
+    if n != gx * gy * gz:
+        raise ValueError("state must hold gx*gy*gz groups")
+    if out is None:
+        out = torch.empty_like(state)
+    _need(out, (NV, NI, NI, NI), state.dtype, "out")
+    for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
+        if t.dtype != torch.float64 or not t.is_cuda or t.numel() < 1:
+            raise ValueError(f"{nm} must be a GPU float64 tensor")
+    work = _work(work, n, state.dtype, state.device)
+    _stream()
+    fn = _native.lib().gamer_rtvd_solve_periodic_f32 if f32 else _native.lib().gamer_rtvd_solve_periodic
+    _native.check(fn(_ptr(state), int(gx), int(gy), int(gz), _ptr(dt_dev), _ptr(dh_dev), float(gamma),
+                     int(order), _ptr(work), work.numel() * work.element_size(), _ptr(out)))
+    return out
+
+
 # ---- two refinement levels ------------------------------------------------
 
 def _dev_scalar(t, name):

@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 29
+    assert len(names) == 34
     for n in names:
         assert hasattr(lib, n), n
         assert n in _native.SIGNATURES, n
@@ -122,6 +122,33 @@ def test_limiting_and_mixed_argument_errors(lib):
     g = lib.gamer_hydro_solve_periodic_mixed
     assert g(P, 0, 2, 2, P, P, 1.4, None, Q, None, None) == E
     assert g(P, 2, 2, 2, P, P, 1.4, None, P, None, None) == E
+
+
+def test_rtvd_argument_errors(lib):
+    E = _native.GAMER_EINVAL
+    Q = ctypes.c_void_p(0x2000)
+    W = ctypes.c_void_p(0x4000)
+    need = lib.gamer_rtvd_workspace_bytes(8, 0)
+    assert need == 8 * 5 * (16 * 22 * 22 + 16 * 16 * 22) * 8
+    assert lib.gamer_rtvd_workspace_bytes(8, 1) == need // 2
+    assert lib.gamer_rtvd_workspace_bytes(0, 0) == 0
+    for f in (lib.gamer_rtvd_solve_batched, lib.gamer_rtvd_solve_batched_f32):
+        assert f(P, -1, None, P, P, 1, 1.4, 0, W, need, Q) == E
+        assert f(P, 8, None, P, P, 1, 1.4, 2, W, need, Q) == E            # order
+        assert f(P, 8, None, P, P, 1, 1.0, 0, W, need, Q) == E            # gamma
+        assert f(None, 8, None, P, P, 1, 1.4, 0, W, need, Q) == E
+        assert f(P, 8, None, None, P, 1, 1.4, 0, W, need, Q) == E
+        assert f(P, 8, None, P, P, 0, 1.4, 0, W, need, Q) == E            # n_levels
+        assert f(P, 8, None, P, P, 1, 1.4, 0, None, need, Q) == E         # no workspace
+        assert f(P, 8, None, P, P, 1, 1.4, 0, W, 100, Q) == E             # short workspace
+        assert b"workspace" in lib.gamer_last_error()
+        assert f(P, 8, None, P, P, 1, 1.4, 0, ctypes.c_void_p(0x4008), need, Q) == E  # misaligned
+        assert f(P, 8, None, P, P, 1, 1.4, 0, W, need, P) == E            # aliased
+        assert f(None, 0, None, None, None, 1, 1.4, 0, None, 0, None) == _native.GAMER_OK
+    for f in (lib.gamer_rtvd_solve_periodic, lib.gamer_rtvd_solve_periodic_f32):
+        assert f(P, 0, 2, 2, P, P, 1.4, 0, W, need, Q) == E
+        assert f(P, 1 << 25, 1, 1, P, P, 1.4, 0, W, need, Q) == E
+        assert f(P, 2, 2, 2, P, P, 1.4, 0, W, need, P) == E
 
 
 def test_periodic_argument_errors(lib):

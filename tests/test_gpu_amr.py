@@ -214,10 +214,11 @@ def test_two_level_step_against_oracle(gpu, dtype):
     dt = 0.4 * oracle.cfl_dt(coarse, dh, G53, 1.0)
     want_c, want_f, _, _ = two_level_step(coarse, g, g, g, fine, parent, faces, dt, dh, G53)
     c_gpu = torch.from_numpy(coarse).to(dtype).to(gpu)
-    before = hydro.conserved_sums(c_gpu, dh)
-    got_c, got_f = gpu_two_level_step(c_gpu, torch.from_numpy(fine).to(dtype).to(gpu),
-                                      torch.from_numpy(parent).to(gpu), amr.faces_to_device(faces, gpu),
-                                      dt, dh, g)
+    f_gpu = torch.from_numpy(fine).to(dtype).to(gpu)
+    parent_t = torch.from_numpy(parent).to(gpu)
+    # composite totals before the step: the fine groups restricted onto the coarse grid
+    before = hydro.conserved_sums(hydro.restrict(f_gpu, parent_t, c_gpu.clone()), dh)
+    got_c, got_f = gpu_two_level_step(c_gpu, f_gpu, parent_t, amr.faces_to_device(faces, gpu), dt, dh, g)
     if dtype == torch.float64:
         close(got_c.cpu().numpy(), want_c, 1e-12, "two-level coarse")
         close(got_f.cpu().numpy(), want_f, 1e-12, "two-level fine")
