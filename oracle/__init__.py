@@ -56,6 +56,7 @@ def _lib():
             "gamer_oracle_conserved_sums": (None, [_PD, _I64, _D, _PD]),
             "gamer_oracle_pack_periodic": (None, [_PD, ctypes.c_int, ctypes.c_int, ctypes.c_int, _PD]),
             "gamer_oracle_vanleer": (_D, [_D, _D]),
+            "gamer_oracle_ctu_solve": (ctypes.c_int, [_PD, _I64, _D, _D, _D, _D, _PD, _PD, _PLL]),
             "gamer_oracle_rtvd_pencil": (ctypes.c_longlong, [_PD, ctypes.c_int, ctypes.c_int, _D, _D, _PD]),
             "gamer_oracle_rtvd_solve": (ctypes.c_int, [_PD, _I64, _D, _D, _D, ctypes.c_int, _PD, _PLL]),
         }
@@ -190,10 +191,19 @@ def group_update(U, Fl, dt, dh, want_planes=False):
 
 # --- batch entry points -----------------------------------------------------
 
-def hydro_solve(groups_in, dt, dh, gamma, theta=THETA, want_fluxes=False, limiting="primitive"):
+def hydro_solve(groups_in, dt, dh, gamma, theta=THETA, want_fluxes=False, limiting="primitive",
+                coupling="hancock"):
     """One step on a batch.  Returns (groups_out, fluxes_or_None, (n_pred_fallback, n_hlle)).
-    limiting: "primitive" or "characteristic" (variables the slopes are limited in)."""
+    limiting: "primitive" or "characteristic" (variables the slopes are limited in);
+    coupling: "hancock" (the unsplit Hancock predictor) or "ctu" (corner transport
+    upwind, gamer_ctu.c; primitive limiting only)."""
     char = {"primitive": 0, "characteristic": 1}[limiting]
+    if coupling == "ctu":
+        if char:
+            raise ValueError("the CTU variant limits primitive variables")
+        return _ctu_solve(groups_in, dt, dh, gamma, theta, want_fluxes)
+    if coupling != "hancock":
+        raise ValueError(coupling)
     g = _f64(groups_in)
     assert g.ndim == 5 and g.shape[1:] == (5, 20, 20, 20), g.shape
     n = g.shape[0]
@@ -204,6 +214,20 @@ def hydro_solve(groups_in, dt, dh, gamma, theta=THETA, want_fluxes=False, limiti
                                              ctypes.cast(counts, _PLL))
     if rc != 0:
         raise ValueError("oracle hydro_solve rejected its arguments")
+    return out, fl, (int(counts[0]), int(counts[1]))
+
+
+def _ctu_solve(groups_in, dt, dh, gamma, theta, want_fluxes):
+    g = _f64(groups_in)
+    assert g.ndim == 5 and g.shape[1:] == (5, 20, 20, 20), g.shape
+    n = g.shape[0]
+    out = np.empty((n, 5, 16, 16, 16))
+    fl = np.empty((n, 3, 3, 5, 16, 16)) if want_fluxes else None
+    counts = (ctypes.c_longlong * 2)()
+    rc = _lib().gamer_oracle_ctu_solve(_p(g), n, dt, dh, gamma, theta, _p(fl), _p(out),
+                                       ctypes.cast(counts, _PLL))
+    if rc != 0:
+        raise ValueError("oracle ctu_solve rejected its arguments")
     return out, fl, (int(counts[0]), int(counts[1]))
 
 
@@ -255,10 +279,11 @@ def pack_periodic_subset(state, gx, gy, gz, ids):
     return out
 
 
-def step_periodic(state, gx, gy, gz, dt, dh, gamma, theta=THETA, limiting="primitive"):
+def step_periodic(state, gx, gy, gz, dt, dh, gamma, theta=THETA, limiting="primitive",
+                  coupling="hancock"):
     """Ghost fill then one step of a uniform periodic grid held as groups."""
     out, _, counts = hydro_solve(pack_periodic(state, gx, gy, gz), dt, dh, gamma, theta,
-                                 limiting=limiting)
+                                 limiting=limiting, coupling=coupling)
     return out, counts
 
 

@@ -9,7 +9,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "gamer_oracle.c")
-SRCS = [SRC, os.path.join(HERE, "gamer_rtvd.c")]
+SRCS = [SRC, os.path.join(HERE, "gamer_rtvd.c"), os.path.join(HERE, "gamer_ctu.c")]
 LIB = os.path.join(HERE, "libgamer_oracle.so")
 
 
