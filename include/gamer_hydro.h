@@ -234,6 +234,37 @@ int gamer_conserved_sums_f32(const float *groups, int64_t n_groups, double dh,
 int gamer_pack_periodic(const double *state, int gx, int gy, int gz, double *padded);
 int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *padded);
 
+/* ---- corner-transport-upwind coupling (a variant of the unsplit step) -----
+ * The paper applies MUSCL-Hancock unsplit (Sec. 2) without saying how the
+ * three directions are coupled.  The default entry points couple them through
+ * the conservative Hancock predictor; this variant couples them as Colella's
+ * (1990) corner transport upwind method does (its six-Riemann-solve form):
+ *  1. slopes as in the default path (primitive, generalised minmod) on the
+ *     cells of [-1,16]^3 with at most two coordinates outside 0..15;
+ *  2. per direction d, face states cons(W -+ dW_d/2) advanced by
+ *     dt/(2dh) [F_d(U^{d,-}) - F_d(U^{d,+})] (direction d alone); if either is
+ *     unphysical both take the cell average (counted in stat 6);
+ *  3. Roe fluxes Ft between every two neighbouring cells of that set;
+ *  4. the states the group's faces use are corrected by
+ *     -dt/(2dh) sum_{d' != d} [Ft_{d'}(c + e_{d'}/2) - Ft_{d'}(c - e_{d'}/2)]; a
+ *     corrected state that is unphysical keeps its step-2 value (stat 6);
+ *  5. Roe fluxes at the 3 x 17 x 16^2 faces and the default full-step update.
+ * HLLE fallbacks of steps 3 and 5 are counted in stat 7.  Arguments, layouts
+ * and outputs as in gamer_hydro_solve_batched (padded input); opts may set
+ * theta only.  work: device workspace of gamer_ctu_workspace_bytes(n, f32)
+ * bytes, 256-byte aligned, owned by the caller; the call launches five
+ * kernels and allocates nothing.  Errors as the batched step, plus a missing,
+ * short or misaligned workspace and opts fields other than theta. */
+size_t gamer_ctu_workspace_bytes(int64_t n_groups, int f32);
+int gamer_ctu_solve_batched(const double *groups_in, int64_t n_groups, const int8_t *level,
+                            const double *dt_dev, const double *dh_dev, int n_levels, double gamma,
+                            double *fluxes_out, double *groups_out, double *group_stats,
+                            const gamer_opts *opts, void *work, size_t work_bytes);
+int gamer_ctu_solve_batched_f32(const float *groups_in, int64_t n_groups, const int8_t *level,
+                                const double *dt_dev, const double *dh_dev, int n_levels, double gamma,
+                                float *fluxes_out, float *groups_out, double *group_stats,
+                                const gamer_opts *opts, void *work, size_t work_bytes);
+
 /* ---- the relaxing TVD scheme (the solver the paper compares with) --------
  * The paper's Sec. 2 compares MUSCL-Hancock with the scheme GAMER used
  * before: the second-order relaxing total-variation-diminishing scheme of

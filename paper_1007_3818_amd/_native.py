@@ -58,6 +58,10 @@ SIGNATURES = {
     "gamer_conserved_sums_f32": (_I, [_P, _I64, _D, _P, _I]),
     "gamer_pack_periodic": (_I, [_P, _I, _I, _I, _P]),
     "gamer_pack_periodic_f32": (_I, [_P, _I, _I, _I, _P]),
+    "gamer_ctu_workspace_bytes": (ctypes.c_size_t, [_I64, _I]),
+    "gamer_ctu_solve_batched": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO, _P, ctypes.c_size_t]),
+    "gamer_ctu_solve_batched_f32": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO, _P,
+                                         ctypes.c_size_t]),
     "gamer_rtvd_workspace_bytes": (ctypes.c_size_t, [_I64, _I]),
     "gamer_rtvd_solve_batched": (_I, [_P, _I64, _P, _P, _P, _I, _D, _I, _P, ctypes.c_size_t, _P]),
     "gamer_rtvd_solve_batched_f32": (_I, [_P, _I64, _P, _P, _P, _I, _D, _I, _P, ctypes.c_size_t, _P]),

@@ -13,8 +13,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgamer_hydro.so")
-SOURCES = ["solver.hip", "aux_kernels.hip", "amr.hip", "rtvd.hip", "abi.hip"]
-HEADERS = ["internal.h", "device_math.h"]
+SOURCES = ["solver.hip", "ctu.hip", "aux_kernels.hip", "amr.hip", "rtvd.hip", "abi.hip"]
+HEADERS = ["internal.h", "device_math.h", "euler.h"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -277,6 +277,32 @@ int restrict_common(const T *fine, const int64_t *parent, int64_t n_fine, T *coa
 }
 
 template <typename T>
+int ctu_common(const T *in, int64_t n, const int8_t *level, const double *dt_dev, const double *dh_dev,
+               int n_levels, double gamma, T *fluxes, T *out, double *stats, const gamer_opts *opts,
+               void *work, size_t work_bytes) {
+    g_err[0] = 0;
+    if (n < 0) return fail(GAMER_EINVAL, "n_groups < 0");
+    if (!(isfinite(gamma) && gamma > 1.0)) return fail(GAMER_EINVAL, "gamma must be > 1");
+    double theta;
+    int variant, limiting;
+    int64_t grid;
+    if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting)) return e;
+    if (variant != 0 || grid != 0 || limiting != GAMER_LIMIT_PRIMITIVE)
+        return fail(GAMER_EINVAL, "the CTU step takes theta only (variant, grid 0; primitive limiting)");
+    if (n == 0) return GAMER_OK;
+    if (!in || !out || !dt_dev || !dh_dev) return fail(GAMER_EINVAL, "NULL array argument");
+    if (n_levels < 1 || n_levels > GAMER_MAX_LEVELS)
+        return fail(GAMER_EINVAL, "n_levels must lie in [1, %d]", GAMER_MAX_LEVELS);
+    const size_t need = ctu_workspace_bytes(n, int(sizeof(T)));
+    if (!work || work_bytes < need) return fail(GAMER_EINVAL, "workspace of %zu bytes required", need);
+    if (reinterpret_cast<uintptr_t>(work) % 256) return fail(GAMER_EINVAL, "workspace must be 256-byte aligned");
+    if (n * 51 > INT32_MAX) return fail(GAMER_EINVAL, "too many groups for one launch");
+    return check_hip(launch_ctu<T>(in, n, level, dt_dev, dh_dev, gamma, theta, fluxes, out, stats, work,
+                                   g_stream),
+                     "CTU launch");
+}
+
+template <typename T>
 int rtvd_common(const T *in, int gx, int gy, int gz, int64_t n, const int8_t *level,
                 const double *dt_dev, const double *dh_dev, int n_levels, double gamma, int order,
                 void *work, size_t work_bytes, T *out) {
@@ -453,6 +479,27 @@ int gamer_pack_periodic(const double *state, int gx, int gy, int gz, double *pad
 
 int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *padded) {
     return pack_common<float>(state, gx, gy, gz, padded);
+}
+
+size_t gamer_ctu_workspace_bytes(int64_t n_groups, int f32) {
+    if (n_groups <= 0) return 0;
+    return ctu_workspace_bytes(n_groups, f32 ? 4 : 8);
+}
+
+int gamer_ctu_solve_batched(const double *groups_in, int64_t n_groups, const int8_t *level,
+                            const double *dt_dev, const double *dh_dev, int n_levels, double gamma,
+                            double *fluxes_out, double *groups_out, double *group_stats,
+                            const gamer_opts *opts, void *work, size_t work_bytes) {
+    return ctu_common<double>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, gamma, fluxes_out,
+                              groups_out, group_stats, opts, work, work_bytes);
+}
+
+int gamer_ctu_solve_batched_f32(const float *groups_in, int64_t n_groups, const int8_t *level,
+                                const double *dt_dev, const double *dh_dev, int n_levels, double gamma,
+                                float *fluxes_out, float *groups_out, double *group_stats,
+                                const gamer_opts *opts, void *work, size_t work_bytes) {
+    return ctu_common<float>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, gamma, fluxes_out,
+                             groups_out, group_stats, opts, work, work_bytes);
 }
 
 size_t gamer_rtvd_workspace_bytes(int64_t n_groups, int f32) {

@@ -1,0 +1,350 @@
+// ctu.hip -- the corner-transport-upwind (CTU) coupling of the MUSCL-Hancock
+// step: face states predicted along their own direction, corrected by upwind
+// transverse Roe fluxes, then the final Roe fluxes and the same full-step
+// update as the default path.  Unlike the fused z-sweep solver this variant
+// keeps its intermediate arrays in a caller-provided workspace and runs as a
+// short pipeline of launches, one stage each:
+//   ctu_zero      clear the per-group fallback counters
+//   ctu_predict   slopes and the one-direction Hancock predictor on the cells
+//                 of [-1,16]^3 with at most two coordinates outside the
+//                 interior (set E1)                          -> Ub [6][5][18^3]
+//   ctu_transverse  Roe fluxes between neighbouring E1 cells -> Ft [3][5][18^3]
+//   ctu_final     corrected states and the final Roe fluxes   -> Fl [3][5][17][16][16]
+//   ctu_update    U - dt/dh ((dF_x + dF_y) + dF_z) and the per-group stats
+#include "device_math.h"
+#include "euler.h"
+#include "internal.h"
+
+namespace gamer {
+namespace {
+
+constexpr int CE = 18;                        // cells -1..16 per axis
+constexpr int NINNER = NI * NI;
+constexpr int64_t E3 = int64_t(CE) * CE * CE;  // 5832
+constexpr int64_t UB_VALUES = 6 * NV * E3;
+constexpr int64_t FT_VALUES = 3 * NV * E3;
+constexpr int64_t FL_VALUES = 3 * NV * 17 * NI * NI;
+constexpr int64_t WORK_VALUES = UB_VALUES + FT_VALUES + FL_VALUES;  // per group
+
+__device__ __forceinline__ int eidx(int i, int j, int k) { return ((k + 1) * CE + (j + 1)) * CE + (i + 1); }
+__device__ __forceinline__ int n_out(int i, int j, int k) {
+    return (i < 0 || i >= NI) + (j < 0 || j >= NI) + (k < 0 || k >= NI);
+}
+__device__ __forceinline__ bool in_e1(int i, int j, int k) {
+    return i >= -1 && i <= NI && j >= -1 && j <= NI && k >= -1 && k <= NI && n_out(i, j, k) <= 2;
+}
+
+template <typename T>
+struct CtuArgs {
+    const T *in;          // [n][5][20][20][20]
+    T *out;               // [n][5][16][16][16]
+    T *flux;              // [n][3][3][5][16][16] or nullptr
+    double *stats;        // [n][8] or nullptr
+    const int8_t *level;
+    const double *dt_dev, *dh_dev;
+    double gamma, theta;
+    int64_t n_groups;
+    T *work;              // [n][WORK_VALUES]
+    int *counts;          // [n][2]
+};
+
+template <typename T>
+__device__ __forceinline__ void group_dt(const CtuArgs<T> &P, int64_t g, double &dt, double &dh) {
+    const int lev = P.level ? int(P.level[g]) : 0;
+    dt = P.dt_dev[lev];
+    dh = P.dh_dev[lev];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void ctu_zero(CtuArgs<T> P) {
+    const int64_t q = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (q < 2 * P.n_groups) P.counts[q] = 0;
+}
+
+template <int D>
+__device__ __forceinline__ void nb(int s, int &i, int &j, int &k) {
+    if (D == 0) i += s;
+    if (D == 1) j += s;
+    if (D == 2) k += s;
+}
+
+// primitive state of padded cell (i, j, k)
+template <typename T>
+__device__ __forceinline__ void prim_at(const T *U, int i, int j, int k, const Consts<T> &c, T w[NV]) {
+    const int o = ((k + NG) * NP + (j + NG)) * NP + (i + NG);
+    const T r = U[o];
+    const T ir = rcp(r);
+    const T u = U[o + 1 * NP * NP * NP] * ir, v = U[o + 2 * NP * NP * NP] * ir,
+            wz = U[o + 3 * NP * NP * NP] * ir;
+    w[0] = r;
+    w[1] = u;
+    w[2] = v;
+    w[3] = wz;
+    w[4] = c.gm1 * (U[o + 4 * NP * NP * NP] - c.half * r * (u * u + v * v + wz * wz));
+}
+
+template <int D, typename T>
+__device__ __forceinline__ bool predict_dir(const T *U, int i, int j, int k, const T W0[NV], T hdt,
+                                            const Consts<T> &c, T um[NV], T up[NV]) {
+    int im = i, jm = j, km = k, iq = i, jq = j, kq = k;
+    nb<D>(-1, im, jm, km);
+    nb<D>(+1, iq, jq, kq);
+    T wl[NV], wr[NV], wm[NV], wp[NV], fm[NV], fp[NV];
+    prim_at(U, im, jm, km, c, wl);
+    prim_at(U, iq, jq, kq, c, wr);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const T dw = limiter(W0[v] - wl[v], wr[v] - W0[v], c.theta);
+        wm[v] = W0[v] - c.half * dw;
+        wp[v] = W0[v] + c.half * dw;
+    }
+    cons_prim(wm, c, um);
+    cons_prim(wp, c, up);
+    flux_prim<D>(wm, c, fm);
+    flux_prim<D>(wp, c, fp);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const T s = hdt * (fm[v] - fp[v]);
+        um[v] += s;
+        up[v] += s;
+    }
+    return physical(um) && physical(up);
+}
+
+// blocks: n * 18 (one plane k = -1..16 each); threads loop over the 18 x 18 cells
+template <typename T>
+__global__ __launch_bounds__(256) void ctu_predict(CtuArgs<T> P) {
+    const int64_t g = blockIdx.x / CE;
+    const int k = int(blockIdx.x % CE) - 1;
+    if (g >= P.n_groups) return;
+    const Consts<T> c = make_consts<T>(P.gamma, P.theta);
+    double dt, dh;
+    group_dt(P, g, dt, dh);
+    const T hdt = T(0.5 * dt / dh);
+    const T *U = P.in + g * GIN;
+    T *Ub = P.work + g * WORK_VALUES;
+    int bad = 0;
+    for (int q = threadIdx.x; q < CE * CE; q += 256) {
+        const int i = q % CE - 1, j = q / CE - 1;
+        if (!in_e1(i, j, k)) continue;
+        T W0[NV];
+        prim_at(U, i, j, k, c, W0);
+        const int e = eidx(i, j, k);
+        const int o = ((k + NG) * NP + (j + NG)) * NP + (i + NG);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            T um[NV], up[NV];
+            const bool ok = d == 0   ? predict_dir<0>(U, i, j, k, W0, hdt, c, um, up)
+                            : d == 1 ? predict_dir<1>(U, i, j, k, W0, hdt, c, um, up)
+                                     : predict_dir<2>(U, i, j, k, W0, hdt, c, um, up);
+            if (!ok) {
+                ++bad;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) um[v] = up[v] = U[o + v * NP * NP * NP];
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                Ub[((2 * d + 0) * NV + v) * E3 + e] = um[v];
+                Ub[((2 * d + 1) * NV + v) * E3 + e] = up[v];
+            }
+        }
+    }
+    if (bad) atomicAdd(P.counts + 2 * g, bad);
+}
+
+// blocks: n * 18 planes; Roe fluxes at faces c + e_d/2 between two E1 cells
+template <typename T>
+__global__ __launch_bounds__(256) void ctu_transverse(CtuArgs<T> P) {
+    const int64_t g = blockIdx.x / CE;
+    const int k = int(blockIdx.x % CE) - 1;
+    if (g >= P.n_groups) return;
+    const Consts<T> c = make_consts<T>(P.gamma, P.theta);
+    const T *Ub = P.work + g * WORK_VALUES;
+    T *Ft = P.work + g * WORK_VALUES + UB_VALUES;
+    int bad = 0;
+    for (int q = threadIdx.x; q < CE * CE; q += 256) {
+        const int i = q % CE - 1, j = q / CE - 1;
+        if (!in_e1(i, j, k)) continue;
+        const int e = eidx(i, j, k);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int iq = i, jq = j, kq = k;
+            if (d == 0) ++iq;
+            if (d == 1) ++jq;
+            if (d == 2) ++kq;
+            if (!in_e1(iq, jq, kq)) continue;
+            const int eq = eidx(iq, jq, kq);
+            T L[NV], R[NV], F[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                L[v] = Ub[((2 * d + 1) * NV + v) * E3 + e];
+                R[v] = Ub[((2 * d + 0) * NV + v) * E3 + eq];
+            }
+            const bool fb = d == 0 ? roe_dir<0>(L, R, c, F) : d == 1 ? roe_dir<1>(L, R, c, F)
+                                                                    : roe_dir<2>(L, R, c, F);
+            bad += fb;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Ft[(d * NV + v) * E3 + e] = F[v];
+        }
+    }
+    if (bad) atomicAdd(P.counts + 2 * g + 1, bad);
+}
+
+// corrected state of direction D, side s, at cell (i, j, k); false when the
+// correction would make it unphysical (the predicted state is kept)
+template <int D, typename T>
+__device__ __forceinline__ bool corrected(const T *Ub, const T *Ft, int s, int i, int j, int k, T hdt,
+                                          T u[NV]) {
+    const int e = eidx(i, j, k);
+    T corr[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) corr[v] = T(0);
+#pragma unroll
+    for (int dd = 0; dd < 3; ++dd) {
+        if (dd == D) continue;
+        const int em = dd == 0 ? eidx(i - 1, j, k) : dd == 1 ? eidx(i, j - 1, k) : eidx(i, j, k - 1);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) corr[v] += Ft[(dd * NV + v) * E3 + e] - Ft[(dd * NV + v) * E3 + em];
+    }
+    T p[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        p[v] = Ub[((2 * D + s) * NV + v) * E3 + e];
+        u[v] = p[v] - hdt * corr[v];
+    }
+    if (physical(u)) return true;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = p[v];
+    return false;
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void final_face(const CtuArgs<T> &P, int64_t g, int f, int t1, int t2, T hdt,
+                                           const Consts<T> &c, int &n_pred, int &n_roe) {
+    const T *Ub = P.work + g * WORK_VALUES;
+    const T *Ft = Ub + UB_VALUES;
+    T *Fl = P.work + g * WORK_VALUES + UB_VALUES + FT_VALUES;
+    int i, j, k;
+    if (D == 0) { i = f; j = t1; k = t2; }
+    else if (D == 1) { i = t1; j = f; k = t2; }
+    else { i = t1; j = t2; k = f; }
+    int il = i, jl = j, kl = k;
+    nb<D>(-1, il, jl, kl);
+    T L[NV], R[NV], F[NV];
+    n_pred += !corrected<D>(Ub, Ft, 1, il, jl, kl, hdt, L);
+    n_pred += !corrected<D>(Ub, Ft, 0, i, j, k, hdt, R);
+    n_roe += roe_dir<D>(L, R, c, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fl[((D * NV + v) * 17 + f) * NINNER + t2 * NI + t1] = F[v];
+    if (P.flux && (f & 7) == 0) {
+        T *dst = P.flux + g * GFLX + ((D * 3 + (f >> 3)) * NV) * NINNER + t2 * NI + t1;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) dst[v * NINNER] = F[v];
+    }
+}
+
+// blocks: n * 3 * 17 (direction, face index); thread = transverse position
+template <typename T>
+__global__ __launch_bounds__(256) void ctu_final(CtuArgs<T> P) {
+    const int64_t g = blockIdx.x / 51;
+    const int r = int(blockIdx.x % 51);
+    const int d = r / 17, f = r % 17;
+    if (g >= P.n_groups) return;
+    const Consts<T> c = make_consts<T>(P.gamma, P.theta);
+    double dt, dh;
+    group_dt(P, g, dt, dh);
+    const T hdt = T(0.5 * dt / dh);
+    const int t1 = threadIdx.x & 15, t2 = threadIdx.x >> 4;
+    int n_pred = 0, n_roe = 0;
+    if (d == 0) final_face<0>(P, g, f, t1, t2, hdt, c, n_pred, n_roe);
+    else if (d == 1) final_face<1>(P, g, f, t1, t2, hdt, c, n_pred, n_roe);
+    else final_face<2>(P, g, f, t1, t2, hdt, c, n_pred, n_roe);
+    if (n_pred) atomicAdd(P.counts + 2 * g, n_pred);
+    if (n_roe) atomicAdd(P.counts + 2 * g + 1, n_roe);
+}
+
+// blocks: n; thread = interior column (i, j), loop over k
+template <typename T>
+__global__ __launch_bounds__(256) void ctu_update(CtuArgs<T> P) {
+    __shared__ double red[256 * NSTAT];
+    const int64_t g = blockIdx.x;
+    if (g >= P.n_groups) return;
+    const Consts<T> c = make_consts<T>(P.gamma, P.theta);
+    double dt, dh;
+    group_dt(P, g, dt, dh);
+    const double dtdh = dt / dh;
+    const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
+    const T *Fl = P.work + g * WORK_VALUES + UB_VALUES + FT_VALUES;
+    const T *U = P.in + g * GIN;
+    T *out = P.out + g * GOUT;
+    double st[NSTAT];
+#pragma unroll
+    for (int q = 0; q < NSTAT; ++q) st[q] = 0.0;
+    for (int k = 0; k < NI; ++k) {
+        T un[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const T *fx = Fl + ((0 * NV + v) * 17) * NINNER + k * NI + j;   // [f=i][t2=k][t1=j]
+            const T *fy = Fl + ((1 * NV + v) * 17) * NINNER + k * NI + i;   // [f=j][t2=k][t1=i]
+            const T *fz = Fl + ((2 * NV + v) * 17) * NINNER + j * NI + i;   // [f=k][t2=j][t1=i]
+            const double dfx = double(fx[(i + 1) * NINNER]) - double(fx[i * NINNER]);
+            const double dfy = double(fy[(j + 1) * NINNER]) - double(fy[j * NINNER]);
+            const double dfz = double(fz[(k + 1) * NINNER]) - double(fz[k * NINNER]);
+            const double u0 = double(U[v * (NP * NP * NP) + ((k + NG) * NP + (j + NG)) * NP + (i + NG)]);
+            const T o = T(u0 - dtdh * ((dfx + dfy) + dfz));
+            out[v * (NI * NI * NI) + (k * NI + j) * NI + i] = o;
+            un[v] = o;
+            st[v] += double(o);
+        }
+        st[5] = fmax(st[5], double(signal_speed(un[0], un[1], un[2], un[3], un[4], c)));
+    }
+    if (threadIdx.x == 0) {
+        st[6] = double(P.counts[2 * g]);
+        st[7] = double(P.counts[2 * g + 1]);
+    }
+    if (P.stats) block_reduce_stats<256>(st, red, P.stats + g * NSTAT);
+}
+
+}  // namespace
+
+size_t ctu_workspace_bytes(int64_t n, int elem) {
+    // per group: the intermediate arrays, then two int32 counters per group
+    return size_t(n) * size_t(WORK_VALUES) * size_t(elem) + size_t(n) * 2 * sizeof(int) + 256;
+}
+
+template <typename T>
+hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double *dt_dev,
+                      const double *dh_dev, double gamma, double theta, T *fluxes, T *out, double *stats,
+                      void *work, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    CtuArgs<T> P;
+    P.in = in;
+    P.out = out;
+    P.flux = fluxes;
+    P.stats = stats;
+    P.level = level;
+    P.dt_dev = dt_dev;
+    P.dh_dev = dh_dev;
+    P.gamma = gamma;
+    P.theta = theta;
+    P.n_groups = n;
+    P.work = static_cast<T *>(work);
+    // counters after the arrays, 256-byte aligned
+    const size_t off = (size_t(n) * size_t(WORK_VALUES) * sizeof(T) + 255) & ~size_t(255);
+    P.counts = reinterpret_cast<int *>(static_cast<char *>(work) + off);
+    hipLaunchKernelGGL(ctu_zero<T>, dim3(unsigned((2 * n + 255) / 256)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(ctu_predict<T>, dim3(unsigned(n * CE)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(ctu_transverse<T>, dim3(unsigned(n * CE)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(ctu_final<T>, dim3(unsigned(n * 51)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(ctu_update<T>, dim3(unsigned(n)), dim3(256), 0, s, P);
+    return hipGetLastError();
+}
+
+template hipError_t launch_ctu<float>(const float *, int64_t, const int8_t *, const double *,
+                                      const double *, double, double, float *, float *, double *, void *,
+                                      hipStream_t);
+template hipError_t launch_ctu<double>(const double *, int64_t, const int8_t *, const double *,
+                                       const double *, double, double, double *, double *, double *,
+                                       void *, hipStream_t);
+
+}  // namespace gamer

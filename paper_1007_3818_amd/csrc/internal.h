@@ -73,6 +73,14 @@ hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int
                        const double *dt_dev, const double *dh_dev, double gamma, int order, T *work,
                        T *out, hipStream_t s);
 
+// CTU coupling (ctu.hip): workspace bytes for n groups of elem-byte values, and
+// one step of padded groups
+size_t ctu_workspace_bytes(int64_t n, int elem);
+template <typename T>
+hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double *dt_dev,
+                      const double *dh_dev, double gamma, double theta, T *fluxes, T *out, double *stats,
+                      void *work, hipStream_t s);
+
 // two refinement levels (amr.hip)
 template <typename T>
 hipError_t launch_flux_accumulate(const T *fluxes, int64_t n_groups, const double *dt_dev, int reset,

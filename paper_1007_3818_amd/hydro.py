@@ -213,6 +213,48 @@ def pack_periodic(state, gx, gy, gz, out=None):
     return out
 
 
+# ---- corner-transport-upwind coupling --------------------------------------
+
+def ctu_workspace(n_groups, dtype, device):
+    """A workspace tensor of the size gamer_ctu_solve_batched needs (256-byte aligned
+    by torch's allocator)."""
+    nbytes = _native.lib().gamer_ctu_workspace_bytes(int(n_groups), int(_f32(dtype)))
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def ctu_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxes_out=None,
+                      group_stats=None, theta=None, work=None):
+    """One step of padded groups with corner-transport-upwind coupling."""
+    f32 = _f32(groups_in.dtype)
+    _need(groups_in, (NV, NP, NP, NP), groups_in.dtype, "groups_in")
+    n = groups_in.shape[0]
+    if out is None:
+        out = torch.empty((n, NV, NI, NI, NI), dtype=groups_in.dtype, device=groups_in.device)
+    _need(out, (NV, NI, NI, NI), groups_in.dtype, "out")
+    if fluxes_out is not None:
+        _need(fluxes_out, (3, 3, NV, NI, NI), groups_in.dtype, "fluxes_out")
+    if group_stats is not None:
+        _need(group_stats, (8,), torch.float64, "group_stats")
+    if level is not None:
+        if level.dtype != torch.int8 or not level.is_cuda or level.numel() != n:
+            raise ValueError("level must be a GPU int8 tensor with one entry per group")
+    for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
+        if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 1:
+            raise ValueError(f"{nm} must be a 1-D GPU float64 tensor")
+    if work is None:
+        work = ctu_workspace(n, groups_in.dtype, groups_in.device)
+    if not isinstance(work, torch.Tensor) or not work.is_cuda or not work.is_contiguous():
+        raise ValueError("work must be a contiguous GPU tensor")
+    opts = _opts(theta, None, None, None)
+    _stream()
+    fn = _native.lib().gamer_ctu_solve_batched_f32 if f32 else _native.lib().gamer_ctu_solve_batched
+    _native.check(fn(_ptr(groups_in), n, _ptr(level), _ptr(dt_dev), _ptr(dh_dev), dt_dev.numel(),
+                     float(gamma), _ptr(fluxes_out), _ptr(out), _ptr(group_stats),
+                     ctypes.byref(opts) if opts is not None else None, _ptr(work),
+                     work.numel() * work.element_size()))
+    return out
+
+
 # ---- the relaxing TVD scheme ----------------------------------------------
 
 RP = 22  # padded cells per axis of the relaxing TVD scheme

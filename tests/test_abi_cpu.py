@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 34
+    assert len(names) == 37
     for n in names:
         assert hasattr(lib, n), n
         assert n in _native.SIGNATURES, n
@@ -122,6 +122,28 @@ def test_limiting_and_mixed_argument_errors(lib):
     g = lib.gamer_hydro_solve_periodic_mixed
     assert g(P, 0, 2, 2, P, P, 1.4, None, Q, None, None) == E
     assert g(P, 2, 2, 2, P, P, 1.4, None, P, None, None) == E
+
+
+def test_ctu_argument_errors(lib):
+    E = _native.GAMER_EINVAL
+    Q = ctypes.c_void_p(0x2000)
+    W = ctypes.c_void_p(0x4000)
+    need = lib.gamer_ctu_workspace_bytes(8, 0)
+    assert need >= 8 * (6 * 5 * 18 ** 3 + 3 * 5 * 18 ** 3 + 3 * 5 * 17 * 256) * 8
+    assert lib.gamer_ctu_workspace_bytes(0, 1) == 0
+    for f in (lib.gamer_ctu_solve_batched, lib.gamer_ctu_solve_batched_f32):
+        assert f(P, -1, None, P, P, 1, 1.4, None, Q, None, None, W, need) == E
+        assert f(P, 8, None, P, P, 1, 1.0, None, Q, None, None, W, need) == E
+        assert f(None, 8, None, P, P, 1, 1.4, None, Q, None, None, W, need) == E
+        assert f(P, 8, None, None, P, 1, 1.4, None, Q, None, None, W, need) == E
+        assert f(P, 8, None, P, P, 0, 1.4, None, Q, None, None, W, need) == E
+        assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, None, None, need) == E
+        assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, None, W, 1000) == E
+        assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, None, ctypes.c_void_p(0x4010), need) == E
+        for bad in (_native.GamerOpts(1.5, 1, 0, 0, 0), _native.GamerOpts(1.5, 0, 8, 0, 0),
+                    _native.GamerOpts(1.5, 0, 0, 1, 0), _native.GamerOpts(3.0, 0, 0, 0, 0)):
+            assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, ctypes.byref(bad), W, need) == E
+        assert f(None, 0, None, None, None, 1, 1.4, None, None, None, None, None, 0) == _native.GAMER_OK
 
 
 def test_rtvd_argument_errors(lib):
