@@ -299,6 +299,37 @@ def bench_amr(tag, state, g, dh, steps):
     return out
 
 
+def bench_ctu(tag, state, g, dh, steps, warmup):
+    """The CTU-coupled step (five launches through a workspace) on the padded
+    groups of the same grid, at the MUSCL-Hancock CFL time step."""
+    import torch
+    from paper_1007_3818_amd import hydro
+
+    n = g ** 3
+    dev = state.device
+    padded = hydro.pack_periodic(state, g, g, g)
+    dh_dev = torch.full((1,), dh, dtype=torch.float64, device=dev)
+    dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
+    stats = torch.empty((n, 8), dtype=torch.float64, device=dev)
+    hydro.group_stats(state, GAMMA, out=stats)
+    hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev)
+    work = hydro.ctu_workspace(n, state.dtype, dev)
+    out = torch.empty_like(state)
+    for _ in range(warmup):
+        hydro.ctu_solve_batched(padded, None, dt_dev, dh_dev, GAMMA, out=out, group_stats=stats, work=work)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        hydro.ctu_solve_batched(padded, None, dt_dev, dh_dev, GAMMA, out=out, group_stats=stats, work=work)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    del work, padded
+    return {"ms_per_step": ms, "cell_updates_per_s": n * CELLS / (ms * 1e-3),
+            "step": "CTU coupling, padded input resident, five launches through a workspace"}
+
+
 RTVD_VALUES_PER_GROUP = 16 ** 3 + 2 * (16 * 22 * 22) + 2 * (16 * 16 * 22) + 16 ** 3
 
 
@@ -382,6 +413,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-amr", action="store_true", help="skip the coarse/fine kernel timings")
     ap.add_argument("--no-rtvd", action="store_true", help="skip the relaxing TVD timings")
+    ap.add_argument("--no-ctu", action="store_true", help="skip the CTU-coupled step timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--variant", type=int, default=None,
@@ -416,12 +448,18 @@ def main():
         res["f32"] = bench_dtype("f32", state.float(), g, dh, args.steps, args.warmup, shape)
     if args.dtype in ("f64", "both"):
         res["f64"] = bench_dtype("f64", state, g, dh, args.steps, args.warmup, shape)
-    if not args.no_rtvd:
+    extras = n_groups <= 4096  # the variants' workspaces are sized for the 256^3 grid
+    if not args.no_rtvd and extras:
         for tag in list(res):
             progress(f"{tag}: relaxing TVD scheme")
             st = state.float() if tag == "f32" else state
             res[tag]["rtvd"] = bench_rtvd(tag, st, g, dh, args.steps, args.warmup)
-    if not args.no_amr:
+    if not args.no_ctu and extras:
+        for tag in list(res):
+            progress(f"{tag}: CTU coupling")
+            st = state.float() if tag == "f32" else state
+            res[tag]["ctu"] = bench_ctu(tag, st, g, dh, max(args.steps // 5, 3), 1)
+    if not args.no_amr and extras:
         for tag in list(res):
             progress(f"{tag}: coarse/fine correction and restriction kernels")
             st = state.float() if tag == "f32" else state
