@@ -394,6 +394,20 @@ void solve_kernel(SolveParams<S_> P) {
                     }
                 }
             }
+            // The old state of plane k-1 for its update below, all five values
+            // loaded before any of the update's stores (the compiler cannot prove
+            // the arrays distinct, and would otherwise wait out a store before
+            // each load).  Where registers allow (float arithmetic, padded input)
+            // the loads are issued before the barrier, so their latency overlaps
+            // the wait.
+            constexpr bool EARLY = sizeof(T) == 4 && !PERIODIC;
+            S_ uold[NV];
+            auto load_old = [&]() {
+                const S_ *src = cell_ptr(ii + NG, jj + NG, k - 1 + NG);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) uold[v] = src[v * VSTRIDE];
+            };
+            if (EARLY && inner && k >= 1) load_old();
             __syncthreads();  // B3: x / y fluxes visible
 
             if (inner) {
@@ -401,12 +415,12 @@ void solve_kernel(SolveParams<S_> P) {
                     // plane k-1 is complete: U - dt/dh ((dF_x + dF_y) + dF_z)
                     const int kk = k - 1;
                     S_ *dst = P.out + g * GOUT + kk * NINNER + t;
-                    const S_ *src = cell_ptr(ii + NG, jj + NG, kk + NG);
+                    if (!EARLY) load_old();
                     T un[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         const double dfz = double(fzn[v]) - double(fz[v]);
-                        const double r = double(src[v * VSTRIDE]) - dtdh * (S.dxy[v][t] + dfz);
+                        const double r = double(uold[v]) - dtdh * (S.dxy[v][t] + dfz);
                         const S_ o = S_(r);
                         dst[v * NI * NINNER] = o;
                         un[v] = T(o);
