@@ -148,8 +148,9 @@ void solve_kernel(SolveParams<S_> P) {
         // ---- load helpers: positions t and t + NT of a padded plane ----
         const int p0 = t, p1 = t + NT;
         const bool has1 = p1 < NPL;
-        int gp0, gp1 = 0;
+        int gp0;
         const int cp0 = xy_part(p0 % NP, p0 / NP, gp0);
+        int gp1 = gp0;  // threads without a second position reload their first
         const int cp1 = has1 ? xy_part(p1 % NP, p1 / NP, gp1) : cp0;
         T pre0[NV], pre1[NV];
         auto fetch = [&](int plane) {  // plane in -2..17
@@ -159,7 +160,7 @@ void solve_kernel(SolveParams<S_> P) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 pre0[v] = T(s0[v * VSTRIDE]);
-                pre1[v] = has1 ? T(s1[v * VSTRIDE]) : T(1);
+                pre1[v] = T(s1[v * VSTRIDE]);
             }
         };
         auto store = [&](int plane) {  // prefetched conserved -> primitive LDS plane
@@ -189,6 +190,7 @@ void solve_kernel(SolveParams<S_> P) {
         fetch(-1);
         store(-1);
         fetch(0);
+        store(0);
 
         // carried across sweep steps
         T zp[NV];            // +z state of this column at the previous plane
@@ -203,9 +205,14 @@ void solve_kernel(SolveParams<S_> P) {
             fz[v] = T(0);
         }
 
+        // Plane k+2 is fetched into registers at the top of step k and written
+        // to the ring after B3, into the slot of plane k-1, which step k no
+        // longer reads by then.  Consuming it there, before the update's stores
+        // are issued, keeps the wait for the loads from also waiting out those
+        // stores (memory operations complete in issue order).
         for (int k = -1; k <= NI; ++k) {
-            store(k + 1);
-            if (k + 2 <= NI + 1) fetch(k + 2);
+            const bool ahead = k + 2 <= NI + 1;
+            if (ahead) fetch(k + 2);
             __syncthreads();  // B1: plane k+1 visible; planes k-1, k, k+1 in the ring
 
             const bool edge = (k < 0 || k >= NI);
@@ -408,7 +415,8 @@ void solve_kernel(SolveParams<S_> P) {
                 for (int v = 0; v < NV; ++v) uold[v] = src[v * VSTRIDE];
             };
             if (EARLY && inner && k >= 1) load_old();
-            __syncthreads();  // B3: x / y fluxes visible
+            __syncthreads();  // B3: x / y fluxes visible; plane k-1 no longer read
+            if (ahead) store(k + 2);
 
             if (inner) {
                 if (k >= 1) {
