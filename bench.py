@@ -141,8 +141,10 @@ def bench_dtype(tag, state, g, dh, steps, warmup, shape=None):
         "unit": "TFLOP/s",
         "frac": flops / (k_ms * 1e-3) / PEAK[tag],
         "traffic": traffic,
-        "kernel": "solve_kernel<%s, %d, %d>" % (("float" if tag == "f32" else "double"),
-                                                *hydro.solver_variants(padded.dtype)[variant]),
+        # the instantiation as rocprofv3 names it: <storage, arithmetic, threads,
+        # waves per SIMD, periodic input, characteristic limiting>
+        "kernel": "solve_kernel<{0}, {0}, {1}, {2}, false, false>".format(
+            "float" if tag == "f32" else "double", *hydro.solver_variants(padded.dtype)[variant]),
         "kernel_ms": k_ms,
         "flops_per_cell": FLOPS_PER_CELL,
         "algorithmic_bytes_per_cell": bytes_per_group(elem) / CELLS,
