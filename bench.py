@@ -169,13 +169,16 @@ def bench_dtype(tag, state, g, dh, steps, warmup, shape=None):
         torch.cuda.synchronize()
         return t0.elapsed_time(t1) / steps
 
-    # the periodic grid advanced by the fused step (ghost cells read in place)
-    if shape is None:
+    # the periodic grid advanced by the fused step (ghost cells read in place);
+    # above the 256^3 grid the fused and mixed steps reuse the batched step's
+    # tuned shape (tuning them would need two more state-sized arrays)
+    retune = shape is None and n_groups <= 4096
+    if retune:
         progress(f"{tag}: tuning the fused periodic step")
         ftuned = autotune.tune(out, dt_dev, dh_dev, GAMMA, use_cache=False, periodic=(g, g, g))
         fvariant, fgrid = ftuned["variant"], ftuned["grid"]
     else:
-        fvariant, fgrid = shape
+        fvariant, fgrid = variant, grid
     progress(f"{tag}: timing the fused periodic step, variant {fvariant} grid {fgrid}")
 
     def fused_step(cur, nxt):
@@ -188,13 +191,13 @@ def bench_dtype(tag, state, g, dh, steps, warmup, shape=None):
     mixed = None
     if tag == "f64":
         # the same fused periodic step with FP64 state and FP32 arithmetic
-        if shape is None:
+        if retune:
             progress("f64: tuning the FP64-state, FP32-arithmetic periodic step")
             mt = autotune.tune(out, dt_dev, dh_dev, GAMMA, use_cache=False, periodic=(g, g, g),
                                compute=torch.float32)
             mvariant, mgrid = mt["variant"], mt["grid"]
         else:
-            mvariant, mgrid = 0, shape[1]
+            mvariant, mgrid = 0, (shape[1] if shape is not None else 0)
 
         def mixed_step(cur, nxt):
             hydro.hydro_solve_periodic(cur, g, g, g, dt_dev, dh_dev, GAMMA, out=nxt, group_stats=stats,
