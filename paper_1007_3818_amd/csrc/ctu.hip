@@ -9,7 +9,7 @@
 //                 of [-1,16]^3 with at most two coordinates outside the
 //                 interior (set E1)                          -> Ub [6][5][18^3]
 //   ctu_transverse  Roe fluxes between neighbouring E1 cells -> Ft [3][5][18^3]
-//   ctu_final     corrected states and the final Roe fluxes   -> Fl [3][5][17][16][16]
+//   ctu_final     corrected states and the final Roe fluxes   -> Fl (see fl_index)
 //   ctu_update    U - dt/dh ((dF_x + dF_y) + dF_z) and the per-group stats
 #include "device_math.h"
 #include "euler.h"
@@ -218,6 +218,15 @@ __device__ __forceinline__ bool corrected(const T *Ub, const T *Ft, int s, int i
     return false;
 }
 
+// Final face fluxes, per direction with the index that varies fastest in the
+// threads that write and read them: x faces [v][k][j][f] (f = 0..16), y faces
+// [v][f][k][i], z faces [v][f][j][i]; (t1, t2) = (j, k) for x, (i, k) for y,
+// (i, j) for z as in the flux planes.
+__device__ __forceinline__ int fl_index(int D, int v, int f, int t1, int t2) {
+    return D == 0 ? ((0 * NV + v) * NINNER + t2 * NI + t1) * 17 + f
+                  : (D * NV + v) * 17 * NINNER + (f * NI + t2) * NI + t1;
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void final_face(const CtuArgs<T> &P, int64_t g, int f, int t1, int t2, T hdt,
                                            const Consts<T> &c, int &n_pred, int &n_roe) {
@@ -235,7 +244,7 @@ __device__ __forceinline__ void final_face(const CtuArgs<T> &P, int64_t g, int f
     n_pred += !corrected<D>(Ub, Ft, 0, i, j, k, hdt, R);
     n_roe += roe_dir<D>(L, R, c, F);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Fl[((D * NV + v) * 17 + f) * NINNER + t2 * NI + t1] = F[v];
+    for (int v = 0; v < NV; ++v) Fl[fl_index(D, v, f, t1, t2)] = F[v];
     if (P.flux && (f & 7) == 0) {
         T *dst = P.flux + g * GFLX + ((D * 3 + (f >> 3)) * NV) * NINNER + t2 * NI + t1;
 #pragma unroll
@@ -243,22 +252,34 @@ __device__ __forceinline__ void final_face(const CtuArgs<T> &P, int64_t g, int f
     }
 }
 
-// blocks: n * 3 * 17 (direction, face index); thread = transverse position
+// blocks: n * 50 per group: 16 for the x faces (one per k; threads (f, j) with
+// f fastest, 272 of them), 17 for the y faces and 17 for the z faces (one per
+// face index; threads (i, k) or (i, j) with i fastest).  Consecutive threads
+// thus read consecutive cells of the x-fastest state arrays in all three.
+constexpr int FINAL_BLOCKS = 50;
+constexpr int FINAL_THREADS = 17 * NI;  // 272
+
 template <typename T>
-__global__ __launch_bounds__(256) void ctu_final(CtuArgs<T> P) {
-    const int64_t g = blockIdx.x / 51;
-    const int r = int(blockIdx.x % 51);
-    const int d = r / 17, f = r % 17;
+__global__ __launch_bounds__(FINAL_THREADS) void ctu_final(CtuArgs<T> P) {
+    const int64_t g = blockIdx.x / FINAL_BLOCKS;
+    const int r = int(blockIdx.x % FINAL_BLOCKS);
     if (g >= P.n_groups) return;
     const Consts<T> c = make_consts<T>(P.gamma, P.theta);
     double dt, dh;
     group_dt(P, g, dt, dh);
     const T hdt = T(0.5 * dt / dh);
-    const int t1 = threadIdx.x & 15, t2 = threadIdx.x >> 4;
+    const int t = threadIdx.x;
     int n_pred = 0, n_roe = 0;
-    if (d == 0) final_face<0>(P, g, f, t1, t2, hdt, c, n_pred, n_roe);
-    else if (d == 1) final_face<1>(P, g, f, t1, t2, hdt, c, n_pred, n_roe);
-    else final_face<2>(P, g, f, t1, t2, hdt, c, n_pred, n_roe);
+    if (r < NI) {  // x faces of row k = r: thread -> (f, j)
+        const int f = t % 17, j = t / 17;
+        final_face<0>(P, g, f, j, r, hdt, c, n_pred, n_roe);
+    } else if (t < NINNER) {
+        const int d = r < NI + 17 ? 1 : 2;
+        const int f = d == 1 ? r - NI : r - NI - 17;
+        const int t1 = t & 15, t2 = t >> 4;
+        if (d == 1) final_face<1>(P, g, f, t1, t2, hdt, c, n_pred, n_roe);
+        else final_face<2>(P, g, f, t1, t2, hdt, c, n_pred, n_roe);
+    }
     if (n_pred) atomicAdd(P.counts + 2 * g, n_pred);
     if (n_roe) atomicAdd(P.counts + 2 * g + 1, n_roe);
 }
@@ -284,12 +305,9 @@ __global__ __launch_bounds__(256) void ctu_update(CtuArgs<T> P) {
         T un[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const T *fx = Fl + ((0 * NV + v) * 17) * NINNER + k * NI + j;   // [f=i][t2=k][t1=j]
-            const T *fy = Fl + ((1 * NV + v) * 17) * NINNER + k * NI + i;   // [f=j][t2=k][t1=i]
-            const T *fz = Fl + ((2 * NV + v) * 17) * NINNER + j * NI + i;   // [f=k][t2=j][t1=i]
-            const double dfx = double(fx[(i + 1) * NINNER]) - double(fx[i * NINNER]);
-            const double dfy = double(fy[(j + 1) * NINNER]) - double(fy[j * NINNER]);
-            const double dfz = double(fz[(k + 1) * NINNER]) - double(fz[k * NINNER]);
+            const double dfx = double(Fl[fl_index(0, v, i + 1, j, k)]) - double(Fl[fl_index(0, v, i, j, k)]);
+            const double dfy = double(Fl[fl_index(1, v, j + 1, i, k)]) - double(Fl[fl_index(1, v, j, i, k)]);
+            const double dfz = double(Fl[fl_index(2, v, k + 1, i, j)]) - double(Fl[fl_index(2, v, k, i, j)]);
             const double u0 = double(U[v * (NP * NP * NP) + ((k + NG) * NP + (j + NG)) * NP + (i + NG)]);
             const T o = T(u0 - dtdh * ((dfx + dfy) + dfz));
             out[v * (NI * NI * NI) + (k * NI + j) * NI + i] = o;
@@ -335,7 +353,7 @@ hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double 
     hipLaunchKernelGGL(ctu_zero<T>, dim3(unsigned((2 * n + 255) / 256)), dim3(256), 0, s, P);
     hipLaunchKernelGGL(ctu_predict<T>, dim3(unsigned(n * CE)), dim3(256), 0, s, P);
     hipLaunchKernelGGL(ctu_transverse<T>, dim3(unsigned(n * CE)), dim3(256), 0, s, P);
-    hipLaunchKernelGGL(ctu_final<T>, dim3(unsigned(n * 51)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(ctu_final<T>, dim3(unsigned(n * FINAL_BLOCKS)), dim3(FINAL_THREADS), 0, s, P);
     hipLaunchKernelGGL(ctu_update<T>, dim3(unsigned(n)), dim3(256), 0, s, P);
     return hipGetLastError();
 }
