@@ -22,7 +22,15 @@
 //    the consumed LDS state.
 //  - The update of plane k-1 completes at step k, once the z flux above it is
 //    known: U - dt/dh ((dF_x + dF_y) + dF_z), in double for both precisions.
-//  - The next padded plane is prefetched into registers one step ahead.
+//  - Plane k+2 is loaded into registers at the top of step k and written to
+//    the ring after the step's last barrier.  The old state of plane k-1 is
+//    loaded in one batch before the update's stores.  Both orderings keep the
+//    waits for loads from also waiting out earlier output stores (vector memory
+//    operations complete in issue order).
+//  - Template parameters select the storage and arithmetic types (float,
+//    double, or double state with float arithmetic), the input (padded groups
+//    or a periodic grid of unpadded groups read in place) and the limited
+//    variables (primitive or characteristic).
 //  - Per-group stats of the updated cells (sums, max signal speed, fallback
 //    counts) are reduced in a fixed order in the epilogue.
 #include "device_math.h"
