@@ -20,6 +20,11 @@
 //    in registers (the +z state of plane k-1 was kept from the last step of the
 //    sweep), the x and y faces after one barrier, with the flux written over
 //    the consumed LDS state.
+//  - Work between two barriers is spread so that no wave carries more than the
+//    heaviest share: in the 256-thread shape the wave that computed the ghost
+//    layer solves its z faces after the x and y faces, while the x faces 16 (on
+//    wave k+1 mod 4) and the y faces 16 (on wave k+2 mod 4) are solved by
+//    other waves, from right states the ghost-layer wave left in LDS.
 //  - The update of plane k-1 completes at step k, once the z flux above it is
 //    known: U - dt/dh ((dF_x + dF_y) + dF_z), in double for both precisions.
 //  - Plane k+2 is loaded into registers at the top of step k and written to
@@ -47,6 +52,7 @@ struct alignas(16) Lds {
     T w[3][NV][NPL];       // primitive planes, ring indexed by (plane + 3) % 3
     T sx[NV][NI][NI + 1];  // [v][j][f]: +x state of cell f-1, then x flux at face f
     T sy[NV][NI + 1][NI];  // [v][f][i]: +y state of cell f-1, then y flux at face f
+    T rf[2][NV][NI];       // -x state of ghost cell (16, j), -y state of ghost cell (i, 16)
     double dxy[NV][NINNER];  // (dF_x + dF_y) of each interior cell of the previous plane
 };
 
@@ -230,7 +236,7 @@ void solve_kernel(SolveParams<S_> P) {
             // ---- face states: the interior cell, then the ghost-layer cell ----
             // (one code path for both, so a face state is computed identically
             // wherever its cell sits)
-            T xm[NV], ym[NV], zm[NV], zpn[NV], rs[NV];  // rs: kept state of a ghost-layer cell
+            T xm[NV], ym[NV], zm[NV], zpn[NV];
             const T(*wm)[NPL] = S.w[(k + 2) % 3];
             const T(*w0)[NPL] = S.w[(k + 3) % 3];
             const T(*wq)[NPL] = S.w[(k + 4) % 3];
@@ -317,56 +323,67 @@ void solve_kernel(SolveParams<S_> P) {
 #pragma unroll
                             for (int v = 0; v < NV; ++v) S.sx[v][cj][0] = Ub[0][1][v];
                             break;
-                        case 1:  // -x state of face 16, kept
+                        case 1:  // -x state of face 16
 #pragma unroll
-                            for (int v = 0; v < NV; ++v) rs[v] = Ub[0][0][v];
+                            for (int v = 0; v < NV; ++v) S.rf[0][v][cj] = Ub[0][0][v];
                             break;
                         case 2:  // +y state of face 0
 #pragma unroll
                             for (int v = 0; v < NV; ++v) S.sy[v][0][ci] = Ub[1][1][v];
                             break;
-                        default:  // -y state of face 16, kept
+                        default:  // -y state of face 16
 #pragma unroll
-                            for (int v = 0; v < NV; ++v) rs[v] = Ub[1][0][v];
+                            for (int v = 0; v < NV; ++v) S.rf[1][v][ci] = Ub[1][0][v];
                             break;
                     }
                 }
             }
 
-            // z face between planes k-1 and k (registers only)
+            // z face between planes k-1 and k (registers only).  A wave that
+            // computed ghost-layer cells in this plane solves it after the x and
+            // y faces instead, while the two waves that take the faces 16 are
+            // busy with them, so that no wave does more than one cell and three
+            // Roe solves between two barriers.
             T fzn[NV];
-            if (inner && k >= 0) {
-                n_roe += roe_dir<2>(zp, zm, c, fzn);
-                if (P.flux && (k & 7) == 0) {
-                    S_ *dst = P.flux + g * GFLX + ((2 * 3 + (k >> 3)) * NV) * NINNER + jj * NI + ii;
+            auto solve_z = [&]() {
+                if (inner && k >= 0) {
+                    n_roe += roe_dir<2>(zp, zm, c, fzn);
+                    if (P.flux && (k & 7) == 0) {
+                        S_ *dst = P.flux + g * GFLX + ((2 * 3 + (k >> 3)) * NV) * NINNER + jj * NI + ii;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(fzn[v]);
+                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(fzn[v]);
+                    }
                 }
-            }
-            __syncthreads();  // B2: +x / +y states visible
+            };
+            const bool late_z = !SPLIT && ring >= 0;
+            if (!late_z) solve_z();
+            __syncthreads();  // B2: +x / +y states and the right states of faces 16 visible
+
+            // faces 16: x by wave k+1 mod 4 and y by wave k+2 mod 4 (320 threads:
+            // both by the ghost-layer wave), lanes 0..15
+            const int lane = t & 63;
+            const bool x16 = lane < NI && (SPLIT ? wave == 4 : wave == ((k + 1) & 3));
+            const bool y16 = lane < NI && (SPLIT ? wave == 4 : wave == ((k + 2) & 3));
 
             if (!edge) {
                 // x faces: face ci of each interior cell, then face 16 of each row
 #pragma unroll 1
                 for (int round = 0; round < 2; ++round) {
                     int row, f;
-                    const T *R;
                     if (round == 0) {
                         if (!inner) continue;
                         row = jj;
                         f = ii;
-                        R = xm;
                     } else {
-                        if (ring < 0 || (ring >> 4) != 1) continue;
-                        row = ring & 15;
+                        if (!x16) continue;
+                        row = lane;
                         f = NI;
-                        R = rs;
                     }
                     T UL[NV], UR[NV], F[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         UL[v] = S.sx[v][row][f];
-                        UR[v] = R[v];
+                        UR[v] = round == 0 ? xm[v] : S.rf[0][v][row];
                     }
                     n_roe += roe_dir<0>(UL, UR, c, F);
 #pragma unroll
@@ -381,23 +398,20 @@ void solve_kernel(SolveParams<S_> P) {
 #pragma unroll 1
                 for (int round = 0; round < 2; ++round) {
                     int col, f;
-                    const T *R;
                     if (round == 0) {
                         if (!inner) continue;
                         col = ii;
                         f = jj;
-                        R = ym;
                     } else {
-                        if (ring < 0 || (ring >> 4) != 3) continue;
-                        col = ring & 15;
+                        if (!y16) continue;
+                        col = lane;
                         f = NI;
-                        R = rs;
                     }
                     T UL[NV], UR[NV], F[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         UL[v] = S.sy[v][f][col];
-                        UR[v] = R[v];
+                        UR[v] = round == 0 ? ym[v] : S.rf[1][v][col];
                     }
                     n_roe += roe_dir<1>(UL, UR, c, F);
 #pragma unroll
@@ -409,6 +423,7 @@ void solve_kernel(SolveParams<S_> P) {
                     }
                 }
             }
+            if (late_z) solve_z();
             // The old state of plane k-1 for its update below, all five values
             // loaded before any of the update's stores (the compiler cannot prove
             // the arrays distinct, and would otherwise wait out a store before
