@@ -26,10 +26,16 @@ __device__ __forceinline__ float limiter(float a, float b, float theta) {
     const float inner = __builtin_amdgcn_fmed3f(theta * b, 0.5f * (a + b), 0.0f);
     return __builtin_amdgcn_fmed3f(theta * a, inner, 0.0f);
 }
+// In double, without a branch: bs = b with the sign of a is positive exactly
+// when a and b share a sign, and then |a| + bs = |a + b|; otherwise theta bs <= 0
+// and the clamp at 0 gives a zero slope (of either sign).  The min is taken
+// over the same three values as in the definition, so a nonzero slope is the
+// same bitwise.
 __device__ __forceinline__ double limiter(double a, double b, double theta) {
-    if (a * b <= 0.0) return 0.0;
-    const double m = fmin(theta * fabs(a), fmin(theta * fabs(b), 0.5 * fabs(a + b)));
-    return a > 0.0 ? m : -m;
+    const double aa = fabs(a);
+    const double bs = __builtin_copysign(1.0, a) * b;
+    const double m = fmin(theta * aa, fmin(theta * bs, 0.5 * (aa + bs)));
+    return __builtin_copysign(fmax(m, 0.0), a);
 }
 
 // Limited slope along direction D in characteristic variables: the one-sided
