@@ -240,7 +240,7 @@ void solve_kernel(SolveParams<S_> P) {
             const T(*wm)[NPL] = S.w[(k + 2) % 3];
             const T(*w0)[NPL] = S.w[(k + 3) % 3];
             const T(*wq)[NPL] = S.w[(k + 4) % 3];
-#pragma unroll 1
+#pragma unroll
             for (int round = 0; round < 2; ++round) {
                 int ci, cj;
                 if (round == 0) {
@@ -367,7 +367,7 @@ void solve_kernel(SolveParams<S_> P) {
 
             if (!edge) {
                 // x faces: face ci of each interior cell, then face 16 of each row
-#pragma unroll 1
+#pragma unroll
                 for (int round = 0; round < 2; ++round) {
                     int row, f;
                     if (round == 0) {
@@ -395,7 +395,7 @@ void solve_kernel(SolveParams<S_> P) {
                     }
                 }
                 // y faces: face cj of each interior cell, then face 16 of each column
-#pragma unroll 1
+#pragma unroll
                 for (int round = 0; round < 2; ++round) {
                     int col, f;
                     if (round == 0) {
