@@ -239,11 +239,15 @@ __device__ __forceinline__ bool roe(const T L[NV], const T R[NV], const Consts<T
     }
     const T ab2 = fabs(u);
 
+    // dissipation sum_k |lambda_k| alpha_k K_k: waves 1, 2 and 5 share the
+    // transverse components v and w of their eigenvectors, so those rows take
+    // the sum of the three amplitudes once
     const T c1 = al1 * ab1, c2 = al2 * ab2, c3 = al3 * ab2, c4 = al4 * ab2, c5 = al5 * ab5;
-    F[0] = h * ((L[1] + R[1]) - ((c1 + c2) + c5));
+    const T s125 = (c1 + c2) + c5;
+    F[0] = h * ((L[1] + R[1]) - s125);
     F[1] = h * ((L[1] * uL + pL + R[1] * uR + pR) - ((c1 * (u - a) + c2 * u) + c5 * (u + a)));
-    F[2] = h * ((L[2] * uL + R[2] * uR) - (((c1 * v + c2 * v) + c3) + c5 * v));
-    F[3] = h * ((L[3] * uL + R[3] * uR) - (((c1 * w + c2 * w) + c4) + c5 * w));
+    F[2] = h * ((L[2] * uL + R[2] * uR) - (s125 * v + c3));
+    F[3] = h * ((L[3] * uL + R[3] * uR) - (s125 * w + c4));
     F[4] = h * (((L[4] + pL) * uL + (R[4] + pR) * uR) -
                 ((((c1 * (H - ua) + c2 * (h * q2)) + c3 * v) + c4 * w) + c5 * (H + ua)));
     return false;

@@ -47,6 +47,14 @@ namespace {
 
 constexpr int NINNER = NI * NI;  // 256 interior columns
 
+// Element `off` of a wave-uniform base pointer, for a lane offset known to be
+// non-negative and below 2^32: the access can then take the base in scalar
+// registers and a 32-bit lane offset, with no 64-bit address arithmetic per lane.
+template <typename P>
+__device__ __forceinline__ P &at(P *base, unsigned off) {
+    return base[off];
+}
+
 template <typename T>
 struct alignas(16) Lds {
     T w[3][NV][NPL];       // primitive planes, ring indexed by (plane + 3) % 3
@@ -169,12 +177,20 @@ void solve_kernel(SolveParams<S_> P) {
         T pre0[NV], pre1[NV];
         auto fetch = [&](int plane) {  // plane in -2..17
             const S_ *src = plane_base(plane + NG);
-            const S_ *s0 = src + int64_t(gp0) * GOUT + cp0;
-            const S_ *s1 = src + int64_t(gp1) * GOUT + cp1;
+            if constexpr (!PERIODIC) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                pre0[v] = T(s0[v * VSTRIDE]);
-                pre1[v] = T(s1[v * VSTRIDE]);
+                for (int v = 0; v < NV; ++v) {
+                    pre0[v] = T(at(src + v * VSTRIDE, unsigned(cp0)));
+                    pre1[v] = T(at(src + v * VSTRIDE, unsigned(cp1)));
+                }
+            } else {
+                const S_ *s0 = src + int64_t(gp0) * GOUT + cp0;
+                const S_ *s1 = src + int64_t(gp1) * GOUT + cp1;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    pre0[v] = T(s0[v * VSTRIDE]);
+                    pre1[v] = T(s1[v * VSTRIDE]);
+                }
             }
         };
         auto store = [&](int plane) {  // prefetched conserved -> primitive LDS plane
@@ -433,9 +449,12 @@ void solve_kernel(SolveParams<S_> P) {
             constexpr bool EARLY = sizeof(T) == 4 && !PERIODIC;
             S_ uold[NV];
             auto load_old = [&]() {
-                const S_ *src = cell_ptr(ii + NG, jj + NG, k - 1 + NG);
+                // an interior cell: in the group's own block in both input kinds
+                const S_ *src = PERIODIC ? P.in + g * GOUT + (k - 1) * NINNER
+                                         : P.in + g * GIN + (k - 1 + NG) * NPL + NG * NP + NG;
+                const unsigned off = PERIODIC ? unsigned(t) : unsigned(jj * NP + ii);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) uold[v] = src[v * VSTRIDE];
+                for (int v = 0; v < NV; ++v) uold[v] = at(src + v * VSTRIDE, off);
             };
             if (EARLY && inner && k >= 1) load_old();
             __syncthreads();  // B3: x / y fluxes visible; plane k-1 no longer read
@@ -445,7 +464,7 @@ void solve_kernel(SolveParams<S_> P) {
                 if (k >= 1) {
                     // plane k-1 is complete: U - dt/dh ((dF_x + dF_y) + dF_z)
                     const int kk = k - 1;
-                    S_ *dst = P.out + g * GOUT + kk * NINNER + t;
+                    S_ *dst = P.out + g * GOUT + kk * NINNER;
                     if (!EARLY) load_old();
                     T un[NV];
 #pragma unroll
@@ -453,7 +472,7 @@ void solve_kernel(SolveParams<S_> P) {
                         const double dfz = double(fzn[v]) - double(fz[v]);
                         const double r = double(uold[v]) - dtdh * (S.dxy[v][t] + dfz);
                         const S_ o = S_(r);
-                        dst[v * NI * NINNER] = o;
+                        at(dst + v * NI * NINNER, unsigned(t)) = o;
                         un[v] = T(o);
                         st[v] += double(o);
                     }
