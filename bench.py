@@ -40,6 +40,23 @@ FLOPS = {
 }
 FLOPS_PER_CELL = sum(f * n for f, n in FLOPS.values()) / CELLS
 
+# the CTU coupling of the same method, counted the same way (per group): the
+# one-direction predictor on the 5,824 cells of [-1,16]^3 with at most two
+# coordinates outside the interior, the 16,320 transverse Roe fluxes the
+# corrections use, two corrected states per final face, the final Roe fluxes
+CTU_FLOPS = {
+    "prim": (12, 7752),             # cells the one-direction stencils read
+    "slopes": (105, 5824),
+    "predictor": (285, 5824),       # per direction: face values 15, cons 24, fluxes 12,
+                                    # increment 10, states 10, positivity 24
+    "transverse_roe": (219, 16320),
+    "corrections": (37, 2 * FACES),  # two transverse differences, the update, positivity
+    "final_roe": (219, FACES),
+    "update": (35, CELLS),
+    "cfl_sums": (24, CELLS),
+}
+CTU_FLOPS_PER_CELL = sum(f * n for f, n in CTU_FLOPS.values()) / CELLS
+
 
 def bytes_per_group(elem: int) -> int:
     # read the padded group once, write the interior, 8 doubles of stats
@@ -188,6 +205,25 @@ def bench_dtype(tag, state, g, dh, steps, warmup, shape=None):
 
     ms_fused = timed_loop(fused_step)
 
+    # the same fused step, two steps per captured HIP graph, replayed
+    graph = None
+    if n_groups <= 4096:  # two more state-sized buffers
+        from paper_1007_3818_amd.stepper import PeriodicGrid
+        progress(f"{tag}: timing HIP graph replays of the fused periodic step")
+        pg = PeriodicGrid(out, g, g, g, dh, GAMMA, cfl=CFL, variant=fvariant, grid=fgrid).capture()
+        pg.step(2 * max(1, warmup // 2))
+        pairs = max(1, steps // 2)
+        torch.cuda.synchronize()
+        t0.record()
+        pg.step(2 * pairs)
+        t1.record()
+        torch.cuda.synchronize()
+        ms_graph = t0.elapsed_time(t1) / (2 * pairs)
+        graph = {"ms_per_step": ms_graph, "cell_updates_per_s": cells / (ms_graph * 1e-3),
+                 "step": "fused periodic solve + reduce + device time accumulator, two steps per "
+                         "captured graph"}
+        del pg
+
     mixed = None
     if tag == "f64":
         # the same fused periodic step with FP64 state and FP32 arithmetic
@@ -236,6 +272,7 @@ def bench_dtype(tag, state, g, dh, steps, warmup, shape=None):
                                    "grid evolving"},
         "with_ghost_fill": {"ms_per_step": ms_full, "cell_updates_per_s": cells / (ms_full * 1e-3),
                             "step": "periodic ghost fill + batched solve + reduce, grid evolving"},
+        **({"graph_replay": graph} if graph else {}),
         **({"fp64_state_fp32_arithmetic": mixed} if mixed else {}),
     }
 
@@ -331,11 +368,22 @@ def bench_ctu(tag, state, g, dh, steps, warmup):
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[1]) / steps
     del work, padded
+    achieved = CTU_FLOPS_PER_CELL * n * CELLS / (ms * 1e-3)
     return {"ms_per_step": ms, "cell_updates_per_s": n * CELLS / (ms * 1e-3),
+            "roofline": {"bound": "alu", "flops_per_cell": CTU_FLOPS_PER_CELL,
+                         "achieved": achieved / 1e12, "peak": PEAK[tag] / 1e12, "unit": "TFLOP/s",
+                         "frac": achieved / PEAK[tag], "scope": "whole step, five launches"},
             "step": "CTU coupling, padded input resident, five launches through a workspace"}
 
 
 RTVD_VALUES_PER_GROUP = 16 ** 3 + 2 * (16 * 22 * 22) + 2 * (16 * 16 * 22) + 16 ** 3
+# arithmetic of one sweep over a pencil of 22 cells (16 updated), counted as for
+# the MUSCL-Hancock model: relaxed fluxes (48 per cell) at 22 cells, half step
+# (35) and relaxed fluxes again at 20, second-order fluxes with the van Leer
+# limiter (110 per face) at 17 faces, the update (15) at 16 cells; pencils per
+# group and step: 22 x 22, 16 x 22 and 16 x 16
+RTVD_FLOPS_PER_PENCIL = 22 * 48 + 20 * (35 + 48) + 17 * 110 + 16 * 15
+RTVD_FLOPS_PER_CELL = RTVD_FLOPS_PER_PENCIL * (22 * 22 + 16 * 22 + 16 * 16) / CELLS
 
 
 def bench_rtvd(tag, state, g, dh, steps, warmup):
@@ -373,9 +421,12 @@ def bench_rtvd(tag, state, g, dh, steps, warmup):
     if not bool(torch.isfinite(cur).all()):
         return {"error": "non-finite values after the timed steps", "ms_per_step": ms}
     b = RTVD_VALUES_PER_GROUP * 5 * state.element_size() * n
+    flops = RTVD_FLOPS_PER_CELL * cells
     return {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3),
             "algorithmic_bytes_per_cell": b / cells, "hbm_GBps": b / (ms * 1e-3) / 1e9,
             "hbm_frac": b / (ms * 1e-3) / HBM_PEAK,
+            "flops_per_cell": RTVD_FLOPS_PER_CELL, "alu_TFLOPs": flops / (ms * 1e-3) / 1e12,
+            "alu_frac": flops / (ms * 1e-3) / PEAK[tag],
             "step": "three sweeps (x,y,z / z,y,x alternating), ghost cells read in place, CFL dt of "
                     "the initial state"}
 

@@ -1,10 +1,12 @@
 // rtvd.hip -- the relaxing TVD scheme (the solver the paper compares
 // MUSCL-Hancock with): three dimensionally split sweeps per step, one launch
-// per sweep.  A work-group takes 16 pencils of one group along the sweep
-// direction, stages them in LDS, and advances each pencil by the relaxing
-// scheme's half step and full step; the block shrinks by three cells per side
-// along the sweep direction only, so the three sweeps go 22^3 -> 16 x 22 x 22
-// -> 16 x 16 x 22 -> 16^3 (x, y, z order) through two workspace arrays.
+// per sweep, each advancing every pencil along the sweep direction by the
+// relaxing scheme's half step and full step.  The block shrinks by three cells
+// per side along the sweep direction only, so the three sweeps go 22^3 ->
+// 16 x 22 x 22 -> 16 x 16 x 22 -> 16^3 (x, y, z order) through two workspace
+// arrays.  x sweeps: a work-group stages 16 pencils in LDS, so that the loads
+// along x coalesce.  y and z sweeps: one thread per pencil, streaming along it
+// in registers, with consecutive threads on consecutive x.
 #include "device_math.h"
 #include "internal.h"
 
@@ -193,6 +195,114 @@ __global__ __launch_bounds__(256) void rtvd_sweep_kernel(SweepArgs<T> P) {
     }
 }
 
+// The same sweep with one thread per pencil, streaming along it: the relaxed
+// fluxes of each cell, its half-step state and each face flux are computed once,
+// in registers, with no LDS and no barrier.  Consecutive threads take
+// consecutive pencils along the fastest transverse axis, so for y and z sweeps
+// the loads and stores of one position are contiguous across the wave.  D is
+// the sweep axis; PERIODIC reads the periodic grid of unpadded groups (first
+// sweep of a step) with the ghost cells taken from the neighbouring groups.
+template <typename T, int D, bool PERIODIC>
+__global__ __launch_bounds__(256) void rtvd_stream_kernel(SweepArgs<T> P) {
+    constexpr int A = D == 0 ? 1 : 0, B = D == 2 ? 1 : 2;  // transverse axes, A fastest
+    const int e[3] = {P.ex, P.ey, P.ez};
+    int eo[3] = {P.ex, P.ey, P.ez};
+    eo[D] -= 2 * RG;
+    const int ea = e[A], npen = e[A] * e[B];
+    const int64_t tid = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (tid >= P.n_groups * npen) return;
+    const int64_t g = tid / npen;
+    const int p = int(tid - g * npen);
+    const int ia = p % ea, ib = p / ea;
+    const int64_t vin = int64_t(e[0]) * e[1] * e[2], vout = int64_t(eo[0]) * eo[1] * eo[2];
+    const int si[3] = {1, e[0], e[0] * e[1]}, so[3] = {1, eo[0], eo[0] * eo[1]};
+
+    // cell s of the pencil (s = 0..21 along D) is src(s)[v * vstride]
+    const T *base[3];  // padded input: one base; periodic: the groups below, at, above along D
+    int64_t vstride;
+    if constexpr (PERIODIC) {
+        const int gx = P.gx, gy = P.gy, gz = P.gz;
+        const int bc[3] = {int(g % gx), int((g / gx) % gy), int(g / (int64_t(gx) * gy))};
+        const int nb[3] = {gx, gy, gz};
+        // transverse global coordinates, wrapped
+        int gc[3], lc[3];
+        const int tr[2] = {A, B}, ti[2] = {ia, ib};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int ax = tr[q], N = nb[ax] * NI;
+            int X = bc[ax] * NI + ti[q] - RG;
+            X = X < 0 ? X + N : (X >= N ? X - N : X);
+            gc[ax] = X / NI;
+            lc[ax] = X % NI;
+        }
+        lc[D] = 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {  // the group along D: below, own, above
+            int G = bc[D] + q - 1;
+            G = G < 0 ? G + nb[D] : (G >= nb[D] ? G - nb[D] : G);
+            gc[D] = G;
+            const int64_t grp = gc[0] + int64_t(gx) * (gc[1] + int64_t(gy) * gc[2]);
+            base[q] = P.in + grp * GOUT + (lc[2] * NI + lc[1]) * NI + lc[0];
+        }
+        vstride = NI * NI * NI;
+    } else {
+        base[0] = base[1] = base[2] = P.in + g * NV * vin + int64_t(ia) * si[A] + int64_t(ib) * si[B];
+        vstride = vin;
+    }
+    T *dst = P.out + g * NV * vout + int64_t(ia) * so[A] + int64_t(ib) * so[B];
+
+    const int lev = P.level ? int(P.level[g]) : 0;
+    const double dtdx = P.dt_dev[lev] / P.dh_dev[lev];
+    const T hdt = T(0.5 * dtdx);
+    const T g_ = T(P.gamma), gm1 = T(P.gamma - 1.0);
+    constexpr int LSTR[3] = {1, NI, NI * NI};  // strides inside an unpadded group
+
+    T u[RP][NV], fr[RP][NV], fl[RP][NV], fr2[RP][NV], fl2[RP][NV], Fc[RP][NV];
+#pragma unroll
+    for (int s = 0; s < RP; ++s) {
+        const T *src;
+        if constexpr (PERIODIC) {
+            const int q = s < RG ? 0 : (s < RG + NI ? 1 : 2);
+            const int l = s < RG ? s + NI - RG : (s < RG + NI ? s - RG : s - RG - NI);
+            src = base[q] + l * LSTR[D];
+        } else {
+            src = base[0] + s * si[D];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[s][v] = src[v * vstride];
+        relax(u[s], D, g_, gm1, fr[s], fl[s]);
+        if (s < 2) continue;
+        // half-step state of cell m = s - 1 and its relaxed fluxes
+        const int m = s - 1;
+        T h[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const T Fp = T(0.5) * (fr[m][v] - fl[m + 1][v]);
+            const T Fm = T(0.5) * (fr[m - 1][v] - fl[m][v]);
+            h[v] = u[m][v] - hdt * (Fp - Fm);
+        }
+        relax(h, D, g_, gm1, fr2[m], fl2[m]);
+        // second-order flux at face c0 + 1/2, c0 = m - 2 (faces 2..18)
+        const int c0 = m - 2;
+        if (c0 < 2) continue;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const T r0 = fr2[c0 - 1][v], r1 = fr2[c0][v], r2 = fr2[c0 + 1][v];
+            const T l1 = fl2[c0][v], l2 = fl2[c0 + 1][v], l3 = fl2[c0 + 2][v];
+            const T R = r1 + vanleer(T(0.5) * (r1 - r0), T(0.5) * (r2 - r1));
+            const T L = l2 + vanleer(T(0.5) * (l1 - l2), T(0.5) * (l2 - l3));
+            Fc[c0][v] = T(0.5) * (R - L);
+        }
+        if (c0 < RG) continue;
+        // update of cell i = c0 (output position i - 3)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double o = double(u[c0][v]) - dtdx * (double(Fc[c0][v]) - double(Fc[c0 - 1][v]));
+            dst[v * vout + int64_t(c0 - RG) * so[D]] = T(o);
+        }
+    }
+}
+
 }  // namespace
 
 template <typename T>
@@ -230,12 +340,27 @@ hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int
         P.n_groups = n;
         const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
         P.tiles = (e[ta] * e[tb] + PEN - 1) / PEN;
-        const int64_t blocks = n * P.tiles;
-        if (blocks > int64_t(1) << 31) return hipErrorInvalidValue;
-        if (P.gx > 0)
-            hipLaunchKernelGGL((rtvd_sweep_kernel<T, true>), dim3(unsigned(blocks)), dim3(256), 0, s, P);
-        else
-            hipLaunchKernelGGL((rtvd_sweep_kernel<T, false>), dim3(unsigned(blocks)), dim3(256), 0, s, P);
+        if (d != 0) {
+            // y and z pencils: one thread each, streaming (contiguous across the wave)
+            const int64_t blocks = (n * e[ta] * e[tb] + 255) / 256;
+            if (blocks > int64_t(1) << 31) return hipErrorInvalidValue;
+            const dim3 gr(static_cast<unsigned>(blocks)), bl(256);
+            if (d == 1) {
+                if (P.gx > 0) hipLaunchKernelGGL((rtvd_stream_kernel<T, 1, true>), gr, bl, 0, s, P);
+                else hipLaunchKernelGGL((rtvd_stream_kernel<T, 1, false>), gr, bl, 0, s, P);
+            } else {
+                if (P.gx > 0) hipLaunchKernelGGL((rtvd_stream_kernel<T, 2, true>), gr, bl, 0, s, P);
+                else hipLaunchKernelGGL((rtvd_stream_kernel<T, 2, false>), gr, bl, 0, s, P);
+            }
+        } else {
+            // x pencils: 16 per work-group through LDS, so that loads along x coalesce
+            const int64_t blocks = n * P.tiles;
+            if (blocks > int64_t(1) << 31) return hipErrorInvalidValue;
+            if (P.gx > 0)
+                hipLaunchKernelGGL((rtvd_sweep_kernel<T, true>), dim3(unsigned(blocks)), dim3(256), 0, s, P);
+            else
+                hipLaunchKernelGGL((rtvd_sweep_kernel<T, false>), dim3(unsigned(blocks)), dim3(256), 0, s, P);
+        }
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
         src = P.out;
