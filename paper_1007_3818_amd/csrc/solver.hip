@@ -85,6 +85,19 @@ struct Variants<double> {
     static constexpr Shape shape[count] = {{256, 2}, {320, 2}};
 };
 
+// Work-groups are dispatched to the 8 XCDs round-robin (work-group b to XCD
+// b mod 8), and each XCD has its own L2.  Launch slot i (work-group b at its
+// k-th pass of the grid-stride loop, i = b + k * gridDim.x, with gridDim.x a
+// multiple of 8 or the whole batch) is mapped to a group so that each XCD
+// takes a contiguous run of groups: neighbouring groups, which read each
+// other's cells as ghost cells, then mostly share an L2.  A bijection on
+// [0, n) for any n.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int64_t xcd_group(int64_t i, int64_t n) {
+    const int64_t x = i % NXCD, j = i / NXCD, q = n / NXCD, r = n % NXCD;
+    return x * q + (x < r ? x : r) + j;
+}
+
 // The 64 cells of the ghost layer just outside the four side faces of a plane,
 // numbered r = 0..63: -x layer (gives the +x state of face 0), +x layer (solves
 // x face 16), -y layer, +y layer.
@@ -119,7 +132,8 @@ void solve_kernel(SolveParams<S_> P) {
 
     const Consts<T> c = make_consts<T>(P.gamma, P.theta);
 
-    for (int64_t g = blockIdx.x; g < P.n_groups; g += gridDim.x) {
+    for (int64_t slot = blockIdx.x; slot < P.n_groups; slot += gridDim.x) {
+        const int64_t g = xcd_group(slot, P.n_groups);
         double dt = P.dt, dh = P.dh;
         if (P.dt_dev) {
             const int lev = P.level ? int(P.level[g]) : 0;
