@@ -439,7 +439,7 @@ def cpu_baseline(padded64_host, dh, dt):
     oracle.set_threads(threads)
     n = padded64_host.shape[0]
     t = time.perf_counter()
-    oracle.hydro_solve(padded64_host, dt, dh, GAMMA)
+    ref, _, _ = oracle.hydro_solve(padded64_host, dt, dh, GAMMA)
     el = time.perf_counter() - t
     what = "all" if n == 4096 else "a sample of"
     # one core on a subset, the paper's single-core comparison
@@ -455,7 +455,45 @@ def cpu_baseline(padded64_host, dh, dt):
         "kind": "oracle",
         "sample": f"{what} {n} groups of the workload, one FP64 step, {threads} OpenMP threads ({el:.2f} s)",
         "one_core": {"value": sub.shape[0] * CELLS / el1, "sample": f"first 128 groups, 1 thread ({el1:.2f} s)"},
-    }
+    }, ref
+
+
+def accuracy(state, g, dh, dt, ref64):
+    """One step of each GPU path against the FP64 oracle on the same input (the
+    oracle's step from the CPU leg; for FP32 the oracle is run again on the
+    float-rounded input).  Errors per value relative to |oracle| + the
+    variable's largest |oracle| (the parity tests' measure), and L1 relative
+    per variable (largest over the five)."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1007_3818_amd import hydro
+
+    def errs(gpu, ref):
+        gpu = np.asarray(gpu, dtype=np.float64)
+        a = np.abs(ref)
+        s = a.max(axis=(0, 2, 3, 4), keepdims=True)
+        d = np.abs(gpu - ref)
+        l1 = d.sum(axis=(0, 2, 3, 4)) / np.maximum(a.sum(axis=(0, 2, 3, 4)), 1e-300)
+        return {"max_rel": float((d / (a + s)).max()), "l1_rel": float(l1.max())}
+
+    dev = state.device
+    dtd = torch.tensor([dt], dtype=torch.float64, device=dev)
+    dhd = torch.tensor([dh], dtype=torch.float64, device=dev)
+    out = {}
+    p64 = hydro.pack_periodic(state, g, g, g)
+    out["fp64"] = errs(hydro.hydro_solve_batched(p64, None, dtd, dhd, GAMMA).cpu().numpy(), ref64)
+    out["fp64_state_fp32_arithmetic"] = errs(
+        hydro.hydro_solve_batched(p64, None, dtd, dhd, GAMMA, compute=torch.float32).cpu().numpy(), ref64)
+    del p64
+    s32 = state.float()
+    ref32, _, _ = oracle.hydro_solve(oracle.pack_periodic(s32.double().cpu().numpy(), g, g, g), dt, dh, GAMMA)
+    out["fp32"] = errs(hydro.hydro_solve_batched(hydro.pack_periodic(s32, g, g, g), None, dtd, dhd, GAMMA)
+                       .cpu().numpy(), ref32)
+    out["fp32"]["oracle_input"] = "float-rounded input"
+    out["fp32_vs_fp64_input"] = errs(
+        hydro.hydro_solve_batched(hydro.pack_periodic(s32, g, g, g), None, dtd, dhd, GAMMA).cpu().numpy(), ref64)
+    return out
 
 
 def main():
@@ -555,7 +593,10 @@ def main():
         else:  # a bounded sample of the large workload: its first 512 groups
             host_pad = oracle.pack_periodic_subset(state, g, g, g, range(512))
         progress("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(host_pad, dh, dt)
+        line["cpu_baseline"], ref = cpu_baseline(host_pad, dh, dt)
+        if n_groups <= 4096:
+            progress("one step of each path against the oracle")
+            line["accuracy"] = accuracy(state, g, dh, dt, ref)
     print(json.dumps(line), flush=True)
 
 
