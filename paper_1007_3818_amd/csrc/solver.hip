@@ -457,10 +457,9 @@ void solve_kernel(SolveParams<S_> P) {
             // The old state of plane k-1 for its update below, all five values
             // loaded before any of the update's stores (the compiler cannot prove
             // the arrays distinct, and would otherwise wait out a store before
-            // each load).  Where registers allow (float arithmetic, padded input)
-            // the loads are issued before the barrier, so their latency overlaps
-            // the wait.
-            constexpr bool EARLY = sizeof(T) == 4 && !PERIODIC;
+            // each load).  With float arithmetic, where registers allow, the loads
+            // are issued before the barrier, so their latency overlaps the wait.
+            constexpr bool EARLY = sizeof(T) == 4;
             S_ uold[NV];
             auto load_old = [&]() {
                 // an interior cell: in the group's own block in both input kinds
