@@ -9,8 +9,10 @@
 //                 of [-1,16]^3 with at most two coordinates outside the
 //                 interior (set E1)                          -> Ub [6][5][18^3]
 //   ctu_transverse  Roe fluxes between neighbouring E1 cells -> Ft [3][5][18^3]
-//   ctu_final     corrected states and the final Roe fluxes   -> Fl (see fl_index)
-//   ctu_update    U - dt/dh ((dF_x + dF_y) + dF_z) and the per-group stats
+//   ctu_final     one work-group per group sweeping z: corrected states and the
+//                 final Roe fluxes of each plane (x and y faces through LDS, z
+//                 faces in registers), then U - dt/dh ((dF_x + dF_y) + dF_z) of
+//                 the plane below and the per-group stats
 #include "device_math.h"
 #include "euler.h"
 #include "internal.h"
@@ -23,8 +25,7 @@ constexpr int NINNER = NI * NI;
 constexpr int64_t E3 = int64_t(CE) * CE * CE;  // 5832
 constexpr int64_t UB_VALUES = 6 * NV * E3;
 constexpr int64_t FT_VALUES = 3 * NV * E3;
-constexpr int64_t FL_VALUES = 3 * NV * 17 * NI * NI;
-constexpr int64_t WORK_VALUES = UB_VALUES + FT_VALUES + FL_VALUES;  // per group
+constexpr int64_t WORK_VALUES = UB_VALUES + FT_VALUES;  // per group
 
 __device__ __forceinline__ int eidx(int i, int j, int k) { return ((k + 1) * CE + (j + 1)) * CE + (i + 1); }
 __device__ __forceinline__ int n_out(int i, int j, int k) {
@@ -218,109 +219,120 @@ __device__ __forceinline__ bool corrected(const T *Ub, const T *Ft, int s, int i
     return false;
 }
 
-// Final face fluxes, per direction with the index that varies fastest in the
-// threads that write and read them: x faces [v][k][j][f] (f = 0..16), y faces
-// [v][f][k][i], z faces [v][f][j][i]; (t1, t2) = (j, k) for x, (i, k) for y,
-// (i, j) for z as in the flux planes.
-__device__ __forceinline__ int fl_index(int D, int v, int f, int t1, int t2) {
-    return D == 0 ? ((0 * NV + v) * NINNER + t2 * NI + t1) * 17 + f
-                  : (D * NV + v) * 17 * NINNER + (f * NI + t2) * NI + t1;
-}
-
+// Final flux along D at the face between cell (i, j, k) - e_D and cell (i, j, k):
+// Roe between the two corrected states; the flux planes at face index 0, 8, 16
+// are written out when requested.
 template <int D, typename T>
-__device__ __forceinline__ void final_face(const CtuArgs<T> &P, int64_t g, int f, int t1, int t2, T hdt,
-                                           const Consts<T> &c, int &n_pred, int &n_roe) {
+__device__ __forceinline__ void final_flux(const CtuArgs<T> &P, int64_t g, int i, int j, int k, T hdt,
+                                           const Consts<T> &c, int &n_pred, int &n_roe, T F[NV]) {
     const T *Ub = P.work + g * WORK_VALUES;
     const T *Ft = Ub + UB_VALUES;
-    T *Fl = P.work + g * WORK_VALUES + UB_VALUES + FT_VALUES;
-    int i, j, k;
-    if (D == 0) { i = f; j = t1; k = t2; }
-    else if (D == 1) { i = t1; j = f; k = t2; }
-    else { i = t1; j = t2; k = f; }
     int il = i, jl = j, kl = k;
     nb<D>(-1, il, jl, kl);
-    T L[NV], R[NV], F[NV];
+    T L[NV], R[NV];
     n_pred += !corrected<D>(Ub, Ft, 1, il, jl, kl, hdt, L);
     n_pred += !corrected<D>(Ub, Ft, 0, i, j, k, hdt, R);
     n_roe += roe_dir<D>(L, R, c, F);
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Fl[fl_index(D, v, f, t1, t2)] = F[v];
+    const int f = D == 0 ? i : (D == 1 ? j : k);
     if (P.flux && (f & 7) == 0) {
+        // transverse order (t1, t2): (j, k) for x, (i, k) for y, (i, j) for z
+        const int t1 = D == 0 ? j : i, t2 = D == 2 ? j : k;
         T *dst = P.flux + g * GFLX + ((D * 3 + (f >> 3)) * NV) * NINNER + t2 * NI + t1;
 #pragma unroll
         for (int v = 0; v < NV; ++v) dst[v * NINNER] = F[v];
     }
 }
 
-// blocks: n * 50 per group: 16 for the x faces (one per k; threads (f, j) with
-// f fastest, 272 of them), 17 for the y faces and 17 for the z faces (one per
-// face index; threads (i, k) or (i, j) with i fastest).  Consecutive threads
-// thus read consecutive cells of the x-fastest state arrays in all three.
-constexpr int FINAL_BLOCKS = 50;
-constexpr int FINAL_THREADS = 17 * NI;  // 272
-
 template <typename T>
-__global__ __launch_bounds__(FINAL_THREADS) void ctu_final(CtuArgs<T> P) {
-    const int64_t g = blockIdx.x / FINAL_BLOCKS;
-    const int r = int(blockIdx.x % FINAL_BLOCKS);
-    if (g >= P.n_groups) return;
-    const Consts<T> c = make_consts<T>(P.gamma, P.theta);
-    double dt, dh;
-    group_dt(P, g, dt, dh);
-    const T hdt = T(0.5 * dt / dh);
-    const int t = threadIdx.x;
-    int n_pred = 0, n_roe = 0;
-    if (r < NI) {  // x faces of row k = r: thread -> (f, j)
-        const int f = t % 17, j = t / 17;
-        final_face<0>(P, g, f, j, r, hdt, c, n_pred, n_roe);
-    } else if (t < NINNER) {
-        const int d = r < NI + 17 ? 1 : 2;
-        const int f = d == 1 ? r - NI : r - NI - 17;
-        const int t1 = t & 15, t2 = t >> 4;
-        if (d == 1) final_face<1>(P, g, f, t1, t2, hdt, c, n_pred, n_roe);
-        else final_face<2>(P, g, f, t1, t2, hdt, c, n_pred, n_roe);
-    }
-    if (n_pred) atomicAdd(P.counts + 2 * g, n_pred);
-    if (n_roe) atomicAdd(P.counts + 2 * g + 1, n_roe);
-}
+struct FinalLds {
+    union {
+        struct {
+            T fx[NV][NI][NI + 1];  // [v][j][f]: x flux at face f of row j
+            T fy[NV][NI + 1][NI];  // [v][f][i]: y flux at face f of column i
+        } f;
+        double red[256 * NSTAT];  // the stats reduction, after the sweep
+    };
+};
 
-// blocks: n; thread = interior column (i, j), loop over k
+// One work-group of 256 threads per group; thread (i, j) owns column (i, j)
+// and sweeps k = 0..16.  At step k: the z face k (below plane k) in registers;
+// the update of plane k - 1, whose x and y flux differences were kept from the
+// previous step; the x and y faces of plane k into LDS (faces 16 by threads
+// 0..15 in a second round); after a barrier, this column's x and y flux
+// differences of plane k.
 template <typename T>
-__global__ __launch_bounds__(256) void ctu_update(CtuArgs<T> P) {
-    __shared__ double red[256 * NSTAT];
+__global__ __launch_bounds__(256) void ctu_final(CtuArgs<T> P) {
+    __shared__ FinalLds<T> S;
     const int64_t g = blockIdx.x;
     if (g >= P.n_groups) return;
     const Consts<T> c = make_consts<T>(P.gamma, P.theta);
     double dt, dh;
     group_dt(P, g, dt, dh);
+    const T hdt = T(0.5 * dt / dh);
     const double dtdh = dt / dh;
-    const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
-    const T *Fl = P.work + g * WORK_VALUES + UB_VALUES + FT_VALUES;
+    const int t = threadIdx.x;
+    const int i = t & 15, j = t >> 4;
     const T *U = P.in + g * GIN;
     T *out = P.out + g * GOUT;
+    int n_pred = 0, n_roe = 0;
     double st[NSTAT];
 #pragma unroll
     for (int q = 0; q < NSTAT; ++q) st[q] = 0.0;
-    for (int k = 0; k < NI; ++k) {
-        T un[NV];
+    T fz[NV];         // z flux below the current plane
+    double dxy[NV];   // (dF_x + dF_y) of this column in the previous plane
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double dfx = double(Fl[fl_index(0, v, i + 1, j, k)]) - double(Fl[fl_index(0, v, i, j, k)]);
-            const double dfy = double(Fl[fl_index(1, v, j + 1, i, k)]) - double(Fl[fl_index(1, v, j, i, k)]);
-            const double dfz = double(Fl[fl_index(2, v, k + 1, i, j)]) - double(Fl[fl_index(2, v, k, i, j)]);
-            const double u0 = double(U[v * (NP * NP * NP) + ((k + NG) * NP + (j + NG)) * NP + (i + NG)]);
-            const T o = T(u0 - dtdh * ((dfx + dfy) + dfz));
-            out[v * (NI * NI * NI) + (k * NI + j) * NI + i] = o;
-            un[v] = o;
-            st[v] += double(o);
+    for (int v = 0; v < NV; ++v) {
+        fz[v] = T(0);
+        dxy[v] = 0.0;
+    }
+    for (int k = 0; k <= NI; ++k) {
+        T fzn[NV];
+        final_flux<2>(P, g, i, j, k, hdt, c, n_pred, n_roe, fzn);
+        if (k >= 1) {
+            // plane k - 1 is complete: U - dt/dh ((dF_x + dF_y) + dF_z)
+            const int kk = k - 1;
+            T un[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double dfz = double(fzn[v]) - double(fz[v]);
+                const double u0 = double(U[v * (NP * NP * NP) + ((kk + NG) * NP + (j + NG)) * NP + (i + NG)]);
+                const T o = T(u0 - dtdh * (dxy[v] + dfz));
+                out[v * (NI * NI * NI) + (kk * NI + j) * NI + i] = o;
+                un[v] = o;
+                st[v] += double(o);
+            }
+            st[5] = fmax(st[5], double(signal_speed(un[0], un[1], un[2], un[3], un[4], c)));
         }
-        st[5] = fmax(st[5], double(signal_speed(un[0], un[1], un[2], un[3], un[4], c)));
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fz[v] = fzn[v];
+        if (k == NI) break;
+        // x and y faces of plane k: face i of row j, face j of column i, then the
+        // faces 16 of the rows and columns
+#pragma unroll
+        for (int round = 0; round < 2; ++round) {
+            if (round == 1 && t >= NI) break;
+            const int fi = round == 0 ? i : NI, row = round == 0 ? j : t;
+            T F[NV];
+            final_flux<0>(P, g, fi, row, k, hdt, c, n_pred, n_roe, F);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) S.f.fx[v][row][fi] = F[v];
+            const int fj = round == 0 ? j : NI, col = round == 0 ? i : t;
+            final_flux<1>(P, g, col, fj, k, hdt, c, n_pred, n_roe, F);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) S.f.fy[v][fj][col] = F[v];
+        }
+        __syncthreads();  // the plane's x and y fluxes visible
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            dxy[v] = (double(S.f.fx[v][j][i + 1]) - double(S.f.fx[v][j][i])) +
+                     (double(S.f.fy[v][j + 1][i]) - double(S.f.fy[v][j][i]));
+        __syncthreads();  // read before the next plane's fluxes overwrite them
     }
-    if (threadIdx.x == 0) {
-        st[6] = double(P.counts[2 * g]);
-        st[7] = double(P.counts[2 * g + 1]);
-    }
-    if (P.stats) block_reduce_stats<256>(st, red, P.stats + g * NSTAT);
+    // fallback counts: this stage's, plus those of the predictor and the
+    // transverse fluxes, added once by thread 0
+    st[6] = double(n_pred) + (t == 0 ? double(P.counts[2 * g]) : 0.0);
+    st[7] = double(n_roe) + (t == 0 ? double(P.counts[2 * g + 1]) : 0.0);
+    if (P.stats) block_reduce_stats<256>(st, S.red, P.stats + g * NSTAT);
 }
 
 }  // namespace
@@ -353,8 +365,7 @@ hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double 
     hipLaunchKernelGGL(ctu_zero<T>, dim3(unsigned((2 * n + 255) / 256)), dim3(256), 0, s, P);
     hipLaunchKernelGGL(ctu_predict<T>, dim3(unsigned(n * CE)), dim3(256), 0, s, P);
     hipLaunchKernelGGL(ctu_transverse<T>, dim3(unsigned(n * CE)), dim3(256), 0, s, P);
-    hipLaunchKernelGGL(ctu_final<T>, dim3(unsigned(n * FINAL_BLOCKS)), dim3(FINAL_THREADS), 0, s, P);
-    hipLaunchKernelGGL(ctu_update<T>, dim3(unsigned(n)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(ctu_final<T>, dim3(unsigned(n)), dim3(256), 0, s, P);
     return hipGetLastError();
 }
 

@@ -129,7 +129,7 @@ def test_ctu_argument_errors(lib):
     Q = ctypes.c_void_p(0x2000)
     W = ctypes.c_void_p(0x4000)
     need = lib.gamer_ctu_workspace_bytes(8, 0)
-    assert need >= 8 * (6 * 5 * 18 ** 3 + 3 * 5 * 18 ** 3 + 3 * 5 * 17 * 256) * 8
+    assert need >= 8 * (6 * 5 * 18 ** 3 + 3 * 5 * 18 ** 3) * 8  # predicted states, transverse fluxes
     assert lib.gamer_ctu_workspace_bytes(0, 1) == 0
     for f in (lib.gamer_ctu_solve_batched, lib.gamer_ctu_solve_batched_f32):
         assert f(P, -1, None, P, P, 1, 1.4, None, Q, None, None, W, need) == E
