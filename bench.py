@@ -342,7 +342,7 @@ def bench_amr(tag, state, g, dh, steps):
 
 
 def bench_ctu(tag, state, g, dh, steps, warmup):
-    """The CTU-coupled step (four launches through a workspace) on the padded
+    """The CTU-coupled step (three launches through a workspace) on the padded
     groups of the same grid, at the MUSCL-Hancock CFL time step."""
     import torch
     from paper_1007_3818_amd import hydro
@@ -372,8 +372,8 @@ def bench_ctu(tag, state, g, dh, steps, warmup):
     return {"ms_per_step": ms, "cell_updates_per_s": n * CELLS / (ms * 1e-3),
             "roofline": {"bound": "alu", "flops_per_cell": CTU_FLOPS_PER_CELL,
                          "achieved": achieved / 1e12, "peak": PEAK[tag] / 1e12, "unit": "TFLOP/s",
-                         "frac": achieved / PEAK[tag], "scope": "whole step, four launches"},
-            "step": "CTU coupling, padded input resident, four launches through a workspace"}
+                         "frac": achieved / PEAK[tag], "scope": "whole step, three launches"},
+            "step": "CTU coupling, padded input resident, three launches through a workspace"}
 
 
 RTVD_VALUES_PER_GROUP = 16 ** 3 + 2 * (16 * 22 * 22) + 2 * (16 * 16 * 22) + 16 ** 3

@@ -8,7 +8,8 @@
 //   ctu_predict   slopes and the one-direction Hancock predictor on the cells
 //                 of [-1,16]^3 with at most two coordinates outside the
 //                 interior (set E1)                          -> Ub [6][5][18^3]
-//   ctu_transverse  Roe fluxes between neighbouring E1 cells -> Ft [3][5][18^3]
+//                 then the Roe fluxes between neighbouring E1 cells
+//                                                            -> Ft [3][5][18^3]
 //   ctu_final     one work-group per group sweeping z: corrected states and the
 //                 final Roe fluxes of each plane (x and y faces through LDS, z
 //                 faces in registers), then U - dt/dh ((dF_x + dF_y) + dF_z) of
@@ -112,7 +113,14 @@ __device__ __forceinline__ bool predict_dir(const T *U, int i, int j, int k, con
     return physical(um) && physical(up);
 }
 
-// blocks: n * 18 (one plane k = -1..16 each); threads loop over the 18 x 18 cells
+// blocks: n * 18, one plane k = -1..16 of one group each; threads loop over the
+// 18 x 18 cells.  First the predicted states of the plane's E1 cells (the
+// one-direction Hancock predictor, per direction) -> Ub; then, after a barrier,
+// the transverse Roe fluxes at the faces c + e_d/2 between two E1 cells whose
+// lower cell lies in the plane -> Ft.  The x and y faces read both states from
+// Ub as this work-group wrote them; for the z face the minus-z state of the
+// cell above, which the next plane's work-group writes, is recomputed here (the
+// same function on the same inputs, so the same value).
 template <typename T>
 __global__ __launch_bounds__(256) void ctu_predict(CtuArgs<T> P) {
     const int64_t g = blockIdx.x / CE;
@@ -124,7 +132,8 @@ __global__ __launch_bounds__(256) void ctu_predict(CtuArgs<T> P) {
     const T hdt = T(0.5 * dt / dh);
     const T *U = P.in + g * GIN;
     T *Ub = P.work + g * WORK_VALUES;
-    int bad = 0;
+    T *Ft = Ub + UB_VALUES;
+    int bad = 0, bad_roe = 0;
     for (int q = threadIdx.x; q < CE * CE; q += 256) {
         const int i = q % CE - 1, j = q / CE - 1;
         if (!in_e1(i, j, k)) continue;
@@ -150,19 +159,7 @@ __global__ __launch_bounds__(256) void ctu_predict(CtuArgs<T> P) {
             }
         }
     }
-    if (bad) atomicAdd(P.counts + 2 * g, bad);
-}
-
-// blocks: n * 18 planes; Roe fluxes at faces c + e_d/2 between two E1 cells
-template <typename T>
-__global__ __launch_bounds__(256) void ctu_transverse(CtuArgs<T> P) {
-    const int64_t g = blockIdx.x / CE;
-    const int k = int(blockIdx.x % CE) - 1;
-    if (g >= P.n_groups) return;
-    const Consts<T> c = make_consts<T>(P.gamma, P.theta);
-    const T *Ub = P.work + g * WORK_VALUES;
-    T *Ft = P.work + g * WORK_VALUES + UB_VALUES;
-    int bad = 0;
+    __syncthreads();  // the plane's predicted states visible to the whole work-group
     for (int q = threadIdx.x; q < CE * CE; q += 256) {
         const int i = q % CE - 1, j = q / CE - 1;
         if (!in_e1(i, j, k)) continue;
@@ -174,21 +171,31 @@ __global__ __launch_bounds__(256) void ctu_transverse(CtuArgs<T> P) {
             if (d == 1) ++jq;
             if (d == 2) ++kq;
             if (!in_e1(iq, jq, kq)) continue;
-            const int eq = eidx(iq, jq, kq);
             T L[NV], R[NV], F[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                L[v] = Ub[((2 * d + 1) * NV + v) * E3 + e];
-                R[v] = Ub[((2 * d + 0) * NV + v) * E3 + eq];
+            for (int v = 0; v < NV; ++v) L[v] = Ub[((2 * d + 1) * NV + v) * E3 + e];
+            if (d < 2) {
+                const int eq = eidx(iq, jq, kq);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) R[v] = Ub[((2 * d + 0) * NV + v) * E3 + eq];
+            } else {  // minus-z state of the cell above
+                T Wq[NV], up[NV];
+                prim_at(U, iq, jq, kq, c, Wq);
+                if (!predict_dir<2>(U, iq, jq, kq, Wq, hdt, c, R, up)) {
+                    const int oq = ((kq + NG) * NP + (jq + NG)) * NP + (iq + NG);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) R[v] = U[oq + v * NP * NP * NP];
+                }
             }
             const bool fb = d == 0 ? roe_dir<0>(L, R, c, F) : d == 1 ? roe_dir<1>(L, R, c, F)
                                                                     : roe_dir<2>(L, R, c, F);
-            bad += fb;
+            bad_roe += fb;
 #pragma unroll
             for (int v = 0; v < NV; ++v) Ft[(d * NV + v) * E3 + e] = F[v];
         }
     }
-    if (bad) atomicAdd(P.counts + 2 * g + 1, bad);
+    if (bad) atomicAdd(P.counts + 2 * g, bad);
+    if (bad_roe) atomicAdd(P.counts + 2 * g + 1, bad_roe);
 }
 
 // corrected state of direction D, side s, at cell (i, j, k); false when the
@@ -364,7 +371,6 @@ hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double 
     P.counts = reinterpret_cast<int *>(static_cast<char *>(work) + off);
     hipLaunchKernelGGL(ctu_zero<T>, dim3(unsigned((2 * n + 255) / 256)), dim3(256), 0, s, P);
     hipLaunchKernelGGL(ctu_predict<T>, dim3(unsigned(n * CE)), dim3(256), 0, s, P);
-    hipLaunchKernelGGL(ctu_transverse<T>, dim3(unsigned(n * CE)), dim3(256), 0, s, P);
     hipLaunchKernelGGL(ctu_final<T>, dim3(unsigned(n)), dim3(256), 0, s, P);
     return hipGetLastError();
 }
