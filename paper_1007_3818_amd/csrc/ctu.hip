@@ -264,9 +264,9 @@ struct FinalLds {
 // One work-group of 256 threads per group; thread (i, j) owns column (i, j)
 // and sweeps k = 0..16.  At step k: the z face k (below plane k) in registers;
 // the update of plane k - 1, whose x and y flux differences were kept from the
-// previous step; the x and y faces of plane k into LDS (faces 16 by threads
-// 0..15 in a second round); after a barrier, this column's x and y flux
-// differences of plane k.
+// previous step; the x and y faces of plane k into LDS (faces 16 by one wave
+// each, rotating); after a barrier, this column's x and y flux differences of
+// plane k.
 template <typename T>
 __global__ __launch_bounds__(256) void ctu_final(CtuArgs<T> P) {
     __shared__ FinalLds<T> S;
@@ -313,20 +313,28 @@ __global__ __launch_bounds__(256) void ctu_final(CtuArgs<T> P) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) fz[v] = fzn[v];
         if (k == NI) break;
-        // x and y faces of plane k: face i of row j, face j of column i, then the
-        // faces 16 of the rows and columns
-#pragma unroll
-        for (int round = 0; round < 2; ++round) {
-            if (round == 1 && t >= NI) break;
-            const int fi = round == 0 ? i : NI, row = round == 0 ? j : t;
+        // x and y faces of plane k: face i of row j and face j of column i; then
+        // the faces 16 of the rows (lanes 0..15 of wave k mod 4) and of the
+        // columns (lanes 0..15 of wave k + 1 mod 4), so that no wave takes both
+        {
             T F[NV];
-            final_flux<0>(P, g, fi, row, k, hdt, c, n_pred, n_roe, F);
+            final_flux<0>(P, g, i, j, k, hdt, c, n_pred, n_roe, F);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) S.f.fx[v][row][fi] = F[v];
-            const int fj = round == 0 ? j : NI, col = round == 0 ? i : t;
-            final_flux<1>(P, g, col, fj, k, hdt, c, n_pred, n_roe, F);
+            for (int v = 0; v < NV; ++v) S.f.fx[v][j][i] = F[v];
+            final_flux<1>(P, g, i, j, k, hdt, c, n_pred, n_roe, F);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) S.f.fy[v][fj][col] = F[v];
+            for (int v = 0; v < NV; ++v) S.f.fy[v][j][i] = F[v];
+            const int wave = t >> 6, lane = t & 63;
+            if (lane < NI && wave == (k & 3)) {
+                final_flux<0>(P, g, NI, lane, k, hdt, c, n_pred, n_roe, F);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) S.f.fx[v][lane][NI] = F[v];
+            }
+            if (lane < NI && wave == ((k + 1) & 3)) {
+                final_flux<1>(P, g, lane, NI, k, hdt, c, n_pred, n_roe, F);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) S.f.fy[v][NI][lane] = F[v];
+            }
         }
         __syncthreads();  // the plane's x and y fluxes visible
 #pragma unroll
