@@ -252,7 +252,7 @@ int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *p
  * HLLE fallbacks of steps 3 and 5 are counted in stat 7.  Arguments, layouts
  * and outputs as in gamer_hydro_solve_batched (padded input); opts may set
  * theta only.  work: device workspace of gamer_ctu_workspace_bytes(n, f32)
- * bytes, 256-byte aligned, owned by the caller; the call launches five
+ * bytes, 256-byte aligned, owned by the caller; the call launches three
  * kernels and allocates nothing.  Errors as the batched step, plus a missing,
  * short or misaligned workspace and opts fields other than theta. */
 size_t gamer_ctu_workspace_bytes(int64_t n_groups, int f32);

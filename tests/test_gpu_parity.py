@@ -259,7 +259,15 @@ def test_workload2_full_size_fp64_and_fp32(gpu):
     dt = 0.5 * dh / 3.0  # fixed, well inside the CFL limit of this flow
     gp = hydro.pack_periodic(st, 16, 16, 16)
     out = hydro.hydro_solve(gp, dt, dh, G53).cpu().numpy()
-    out32 = hydro.hydro_solve(hydro.pack_periodic(st.float(), 16, 16, 16), dt, dh, G53).cpu().double().numpy()
+    gp32 = hydro.pack_periodic(st.float(), 16, 16, 16)
+    o32 = hydro.hydro_solve(gp32, dt, dh, G53)
+    # the launch shapes the benchmark's tuner picks on this batch (FP32: a
+    # persistent grid of 768 work-groups) give bitwise the same result
+    dtd = torch.tensor([dt], dtype=torch.float64, device=gpu)
+    dhd = torch.tensor([dh], dtype=torch.float64, device=gpu)
+    assert torch.equal(hydro.hydro_solve_batched(gp32, None, dtd, dhd, G53, variant=0, grid=768), o32)
+    del gp32
+    out32 = o32.cpu().double().numpy()
     host = st.cpu().numpy()
     del gp
     ora, _, cnt = oracle.hydro_solve(oracle.pack_periodic(host, 16, 16, 16), dt, dh, G53)
