@@ -171,7 +171,12 @@ __device__ __forceinline__ void hlle(const T L[NV], const T R[NV], T uL, T pL, T
 // Arithmetic layout: one reciprocal square root per side gives sqrt(rho) and
 // 1/rho; one of a2 gives a and 1/a; the intermediate states' positivity and
 // rho c come from Q = 2 rho E - |m|^2 (p > 0 <=> Q > 0, (rho c)^2 = gq Q), so
-// they need no reciprocal unless the entropy fix is active on that lane.
+// they need no reciprocal unless the entropy fix is active on that lane.  In
+// double, where a square root is a refined estimate of about fifteen
+// instructions, the entropy fix is tested on squared speeds (c^2 = gamma p /
+// rho, (rho* c*)^2 = gq Q*), and the square roots are taken only on lanes where
+// the fix is active or HLLE is used; in float the square root is one hardware
+// instruction and the speeds are formed directly.
 template <typename T>
 __device__ __forceinline__ bool roe(const T L[NV], const T R[NV], const Consts<T> &c, T F[NV]) {
     const T h = c.half;
@@ -181,7 +186,7 @@ __device__ __forceinline__ bool roe(const T L[NV], const T R[NV], const Consts<T
     const T uR = R[1] * irR, vR = R[2] * irR, wR = R[3] * irR;
     const T pL = c.gm1 * (L[4] - h * (L[1] * uL + L[2] * vL + L[3] * wL));
     const T pR = c.gm1 * (R[4] - h * (R[1] * uR + R[2] * vR + R[3] * wR));
-    const T cL = sqrt_(c.g * pL * irL), cR = sqrt_(c.g * pR * irR);
+    const T c2L = c.g * pL * irL, c2R = c.g * pR * irR;  // squared sound speeds
 
     // Roe averages with weights sqrt(rho): sqrt(rho) u = m / sqrt(rho)
     const T is = rcp(L[0] * qL + R[0] * qR);
@@ -192,7 +197,7 @@ __device__ __forceinline__ bool roe(const T L[NV], const T R[NV], const Consts<T
     const T q2 = u * u + v * v + w * w;
     const T a2 = c.gm1 * (H - h * q2);
     if (!(a2 > T(0))) {
-        hlle(L, R, uL, pL, uR, pR, uL - cL, uR + cR, F);
+        hlle(L, R, uL, pL, uR, pR, uL - sqrt_(c2L), uR + sqrt_(c2R), F);
         return true;
     }
     const T ia = rsq(a2);
@@ -215,27 +220,49 @@ __device__ __forceinline__ bool roe(const T L[NV], const T R[NV], const Consts<T
     const T QL = T(2) * Ls[0] * Ls[4] - (Ls[1] * Ls[1] + Ls[2] * Ls[2] + Ls[3] * Ls[3]);
     const T QR = T(2) * Rs[0] * Rs[4] - (Rs[1] * Rs[1] + Rs[2] * Rs[2] + Rs[3] * Rs[3]);
     if (!(Ls[0] > T(0) && QL > T(0) && Rs[0] > T(0) && QR > T(0))) {
-        hlle(L, R, uL, pL, uR, pR, fmin(uL - cL, u - a), fmax(uR + cR, u + a), F);
+        hlle(L, R, uL, pL, uR, pR, fmin(uL - sqrt_(c2L), u - a), fmax(uR + sqrt_(c2R), u + a), F);
         return true;
     }
-    const T rcLs = sqrt_(c.gq * QL), rcRs = sqrt_(c.gq * QR);  // rho* c*
-
     // Harten-Hyman: wave 1 between L (speed uL - cL) and L* (speed (m* - rho* c*)/rho*),
     // wave 5 between R* (speed (m* + rho* c*)/rho*) and R (speed uR + cR).  The fix is
     // active when |lambda| < lambda - lambda_left or |lambda| < lambda_right - lambda.
     const T lam1 = u - a, lam5 = u + a;
-    const T t1a = lam1 - (uL - cL);
-    const T t1b_r = (Ls[1] - rcLs) - lam1 * Ls[0];  // (lambda_right - lambda) rho*
-    const T t5b = (uR + cR) - lam5;
-    const T t5a_r = lam5 * Rs[0] - (Rs[1] + rcRs);  // (lambda - lambda_left) rho*
     T ab1 = fabs(lam1), ab5 = fabs(lam5);
-    if (ab1 < t1a || ab1 * Ls[0] < t1b_r) {
-        const T e = fmax(t1a, t1b_r * rcp(Ls[0]));
-        ab1 = (lam1 * lam1 + e * e) * (h * rcp(e));
-    }
-    if (ab5 < t5b || ab5 * Rs[0] < t5a_r) {
-        const T e = fmax(t5b, t5a_r * rcp(Rs[0]));
-        ab5 = (lam5 * lam5 + e * e) * (h * rcp(e));
+    if constexpr (sizeof(T) == 4) {
+        const T cL = sqrt_(c2L), cR = sqrt_(c2R);
+        const T rcLs = sqrt_(c.gq * QL), rcRs = sqrt_(c.gq * QR);  // rho* c*
+        const T t1a = lam1 - (uL - cL);
+        const T t1b_r = (Ls[1] - rcLs) - lam1 * Ls[0];  // (lambda_right - lambda) rho*
+        const T t5b = (uR + cR) - lam5;
+        const T t5a_r = lam5 * Rs[0] - (Rs[1] + rcRs);  // (lambda - lambda_left) rho*
+        if (ab1 < t1a || ab1 * Ls[0] < t1b_r) {
+            const T e = fmax(t1a, t1b_r * rcp(Ls[0]));
+            ab1 = (lam1 * lam1 + e * e) * (h * rcp(e));
+        }
+        if (ab5 < t5b || ab5 * Rs[0] < t5a_r) {
+            const T e = fmax(t5b, t5a_r * rcp(Rs[0]));
+            ab5 = (lam5 * lam5 + e * e) * (h * rcp(e));
+        }
+    } else {
+        // with the speeds' square roots isolated the tests read, for wave 1,
+        //   cL > |lam1| - (lam1 - uL)     and   rho* c* < m* - (lam1 + |lam1|) rho*,
+        // and for wave 5
+        //   cR > |lam5| + (lam5 - uR)     and   rho* c* < (lam5 - |lam5|) rho* - m*,
+        // each compared through the squares when its right-hand side is positive
+        const T A1 = ab1 - (lam1 - uL), B1 = Ls[1] - (lam1 + ab1) * Ls[0];
+        const T A5 = ab5 + (lam5 - uR), B5 = (lam5 - ab5) * Rs[0] - Rs[1];
+        if (A1 < T(0) || c2L > A1 * A1 || (B1 > T(0) && c.gq * QL < B1 * B1)) {
+            const T t1a = lam1 - (uL - sqrt_(c2L));
+            const T t1b_r = (Ls[1] - sqrt_(c.gq * QL)) - lam1 * Ls[0];
+            const T e = fmax(t1a, t1b_r * rcp(Ls[0]));
+            ab1 = (lam1 * lam1 + e * e) * (h * rcp(e));
+        }
+        if (A5 < T(0) || c2R > A5 * A5 || (B5 > T(0) && c.gq * QR < B5 * B5)) {
+            const T t5b = (uR + sqrt_(c2R)) - lam5;
+            const T t5a_r = lam5 * Rs[0] - (Rs[1] + sqrt_(c.gq * QR));
+            const T e = fmax(t5b, t5a_r * rcp(Rs[0]));
+            ab5 = (lam5 * lam5 + e * e) * (h * rcp(e));
+        }
     }
     const T ab2 = fabs(u);
 
