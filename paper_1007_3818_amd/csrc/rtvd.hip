@@ -74,8 +74,10 @@ template <typename T, bool PERIODIC>
 __global__ __launch_bounds__(256) void rtvd_sweep_kernel(SweepArgs<T> P) {
     __shared__ RtvdLds<T> S;
     const int t = threadIdx.x;
-    const int64_t g = blockIdx.x / P.tiles;
-    const int tile = blockIdx.x - int(g * P.tiles);
+    // 32-bit index arithmetic: the host caps the launch at 2^31 work-groups
+    const int gi = int(blockIdx.x / unsigned(P.tiles));
+    const int tile = int(blockIdx.x) - gi * P.tiles;
+    const int64_t g = gi;
     if (g >= P.n_groups) return;
     const int d = P.d;
     const int e[3] = {P.ex, P.ey, P.ez};
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(256) void rtvd_sweep_kernel(SweepArgs<T> P) {
         idx[d] = s;
         const T *src;
         if constexpr (PERIODIC) {
-            const int bx = int(g % P.gx), by = int((g / P.gx) % P.gy), bz = int(g / (int64_t(P.gx) * P.gy));
+            const int bx = gi % P.gx, by = (gi / P.gx) % P.gy, bz = gi / (P.gx * P.gy);
             const int NX = P.gx * NI, NY = P.gy * NI, NZ = P.gz * NI;
             int X = bx * NI + idx[0] - RG, Y = by * NI + idx[1] - RG, Z = bz * NI + idx[2] - RG;
             X = X < 0 ? X + NX : (X >= NX ? X - NX : X);
@@ -209,10 +211,12 @@ __global__ __launch_bounds__(256) void rtvd_stream_kernel(SweepArgs<T> P) {
     int eo[3] = {P.ex, P.ey, P.ez};
     eo[D] -= 2 * RG;
     const int ea = e[A], npen = e[A] * e[B];
-    const int64_t tid = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (tid >= P.n_groups * npen) return;
-    const int64_t g = tid / npen;
-    const int p = int(tid - g * npen);
+    // 32-bit index arithmetic: the host caps n_groups * pencils below 2^31
+    const int tid = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (int64_t(tid) >= P.n_groups * npen) return;
+    const int gi = tid / npen;
+    const int p = tid - gi * npen;
+    const int64_t g = gi;
     const int ia = p % ea, ib = p / ea;
     const int64_t vin = int64_t(e[0]) * e[1] * e[2], vout = int64_t(eo[0]) * eo[1] * eo[2];
     const int si[3] = {1, e[0], e[0] * e[1]}, so[3] = {1, eo[0], eo[0] * eo[1]};
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(256) void rtvd_stream_kernel(SweepArgs<T> P) {
     int64_t vstride;
     if constexpr (PERIODIC) {
         const int gx = P.gx, gy = P.gy, gz = P.gz;
-        const int bc[3] = {int(g % gx), int((g / gx) % gy), int(g / (int64_t(gx) * gy))};
+        const int bc[3] = {gi % gx, (gi / gx) % gy, gi / (gx * gy)};
         const int nb[3] = {gx, gy, gz};
         // transverse global coordinates, wrapped
         int gc[3], lc[3];
@@ -342,8 +346,8 @@ hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int
         P.tiles = (e[ta] * e[tb] + PEN - 1) / PEN;
         if (d != 0) {
             // y and z pencils: one thread each, streaming (contiguous across the wave)
+            if (n * e[ta] * e[tb] >= int64_t(1) << 31) return hipErrorInvalidValue;
             const int64_t blocks = (n * e[ta] * e[tb] + 255) / 256;
-            if (blocks > int64_t(1) << 31) return hipErrorInvalidValue;
             const dim3 gr(static_cast<unsigned>(blocks)), bl(256);
             if (d == 1) {
                 if (P.gx > 0) hipLaunchKernelGGL((rtvd_stream_kernel<T, 1, true>), gr, bl, 0, s, P);
