@@ -3,7 +3,8 @@
 Bars: FP64 within 1e-12 relative to (|oracle| + per-variable max) for one
 step in both sweep orders; FP32 within 1e-5 in L1 per variable (the oracle
 runs on the float-rounded input); the periodic entry point (ghost cells read
-in place) equal to the padded one, bitwise in FP64; a uniform state kept
+in place) equal to the padded one, bitwise in FP64, and against the oracle on
+grids one group thick along some axes; a uniform state kept
 bitwise; ten alternating FP64 steps of a smooth flow within 1e-11 of the
 oracle's ten steps.
 """
@@ -74,6 +75,22 @@ def test_one_step_fp64(gpu, name, order):
     close(out.cpu().numpy(), ref, 1e-12, f"{name} order {order}")
     per = hydro.rtvd_solve_periodic(s, gx, gy, gz, dev1(dt, gpu), dev1(dh, gpu), G53, order)
     assert torch.equal(per, out)
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (8, 1, 1), (1, 2, 4)])
+def test_periodic_grid_shapes_fp64(gpu, shape):
+    """Grids one group thick along some axes (the ghost cells then wrap into
+    the group itself or its single neighbour), both sweep orders, against the
+    oracle's three-cell ghost fill."""
+    gx, gy, gz = shape
+    st, dh = W.smooth_modes(n=16 if gx * gy * gz == 1 else 32)
+    host = st.numpy()
+    dt = oracle.cfl_dt(host, dh, G53, 0.4)
+    for order in (0, 1):
+        ref, bad = oracle.rtvd_solve(oracle.pack_periodic_rtvd(host, gx, gy, gz), dt, dh, G53, order)
+        assert bad == 0
+        out = hydro.rtvd_solve_periodic(st.to(gpu), gx, gy, gz, dev1(dt, gpu), dev1(dh, gpu), G53, order)
+        close(out.cpu().numpy(), ref, 1e-12, f"{shape} order {order}")
 
 
 @pytest.mark.parametrize("name", ["sod", "smooth48"])
