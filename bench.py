@@ -344,6 +344,60 @@ def bench_amr(tag, state, g, dh, steps):
     return out
 
 
+def bench_levels(tag, steps, warmup, variant, grid):
+    """Workload 3: 512 + 4096 + 20000 groups of a Sedov blast at dh = 1, 1/2, 1/4 in
+    one batched launch per step, each group reading its level's dt and dh on the
+    device, then the per-level CFL reduce (the batch is not evolved: every step
+    advances the same padded input)."""
+    import torch
+    from paper_1007_3818_amd import hydro, workloads
+
+    dev = torch.device("cuda:0")
+    dt_ = torch.float32 if tag == "f32" else torch.float64
+    levels = workloads.sedov_amr(device=dev)
+    pads, inter, lev = [], [], []
+    for L, (groups, dh, gx, ids) in enumerate(levels):
+        idt = torch.as_tensor(ids, device=dev)
+        full = hydro.pack_periodic(groups.to(dt_), gx, gx, gx)
+        pads.append(full[idt])
+        del full
+        inter.append(groups.to(dt_)[idt])
+        lev.append(torch.full((len(ids),), L, dtype=torch.int8))
+    batch = torch.cat(pads)
+    del pads
+    level = torch.cat(lev).to(dev)
+    n = batch.shape[0]
+    dh_dev = torch.tensor([lv[1] for lv in levels], dtype=torch.float64, device=dev)
+    dt_dev = torch.empty(3, dtype=torch.float64, device=dev)
+    stats = torch.empty((n, 8), dtype=torch.float64, device=dev)
+    hydro.group_stats(torch.cat(inter), GAMMA, out=stats)
+    del inter
+    hydro.step_reduce(stats, level, dh_dev, CFL, dt_out=dt_dev)
+    out = torch.empty((n, 5, 16, 16, 16), dtype=dt_, device=dev)
+    totals = torch.empty(7, dtype=torch.float64, device=dev)
+
+    def step():
+        hydro.hydro_solve_batched(batch, level, dt_dev, dh_dev, GAMMA, out=out, group_stats=stats,
+                                  variant=variant, grid=grid)
+        hydro.step_reduce(stats, level, dh_dev, CFL, dt_out=dt_dev, totals_out=totals)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        step()
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    del batch, out
+    return {"groups": n, "levels": 3, "ms_per_step": ms, "cell_updates_per_s": n * CELLS / (ms * 1e-3),
+            "variant": variant, "grid": grid,
+            "step": "Sedov blast, 3 levels (512 + 4096 + 20000 groups), one batched launch with per-group "
+                    "level dt/dh on the device + per-level CFL reduce"}
+
+
 def bench_ctu(tag, state, g, dh, steps, warmup):
     """The CTU-coupled step (three launches through a workspace) on the padded
     groups of the same grid, at the MUSCL-Hancock CFL time step."""
@@ -511,6 +565,7 @@ def main():
     ap.add_argument("--no-amr", action="store_true", help="skip the coarse/fine kernel timings")
     ap.add_argument("--no-rtvd", action="store_true", help="skip the relaxing TVD timings")
     ap.add_argument("--no-ctu", action="store_true", help="skip the CTU-coupled step timings")
+    ap.add_argument("--no-levels", action="store_true", help="skip the three-level batch (workload 3)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for counter scaling)")
     ap.add_argument("--variant", type=int, default=None,
@@ -561,6 +616,11 @@ def main():
             progress(f"{tag}: coarse/fine correction and restriction kernels")
             st = state.float() if tag == "f32" else state
             res[tag]["amr"] = bench_amr(tag, st, g, dh, max(args.steps, 10))
+    if extras and not args.no_levels:
+        for tag in list(res):
+            progress(f"{tag}: three-level batch (workload 3)")
+            t = res[tag]["tuning"]
+            res[tag]["levels_batch"] = bench_levels(tag, max(args.steps // 5, 5), 2, t["variant"], t["grid"])
     main_tag = "f32" if "f32" in res else "f64"
     m = res[main_tag]
     line = {
