@@ -398,6 +398,52 @@ def bench_levels(tag, steps, warmup, variant, grid):
                     "level dt/dh on the device + per-level CFL reduce"}
 
 
+def bench_cosmo(tag, steps, warmup, variant, grid):
+    """Workload 4: the high-contrast log-normal flow (256^3, 4096 groups, density
+    1e-3..1e4, up to Mach 10), batched step + reduce, with the fallback counts of
+    the first step (positivity guard of the predictor, HLLE in the Riemann solver)."""
+    import torch
+    from paper_1007_3818_amd import hydro, workloads
+
+    dev = torch.device("cuda:0")
+    dt_ = torch.float32 if tag == "f32" else torch.float64
+    state, dh = workloads.cosmo_like(n=256, device=dev)
+    padded = hydro.pack_periodic(state.to(dt_), 16, 16, 16)
+    n = padded.shape[0]
+    dh_dev = torch.full((1,), dh, dtype=torch.float64, device=dev)
+    dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
+    stats = torch.empty((n, 8), dtype=torch.float64, device=dev)
+    totals = torch.empty(7, dtype=torch.float64, device=dev)
+    hydro.group_stats(state.to(dt_), GAMMA, out=stats)
+    del state
+    hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev)
+    out = torch.empty((n, 5, 16, 16, 16), dtype=dt_, device=dev)
+
+    def step():
+        hydro.hydro_solve_batched(padded, None, dt_dev, dh_dev, GAMMA, out=out, group_stats=stats,
+                                  variant=variant, grid=grid)
+        hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev, totals_out=totals)
+
+    step()
+    first = totals.cpu().tolist()
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(steps):
+        step()
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    del padded, out
+    return {"ms_per_step": ms, "cell_updates_per_s": n * CELLS / (ms * 1e-3),
+            "fallbacks_first_step": {"predictor_cells": int(first[5]), "hlle_faces": int(first[6])},
+            "variant": variant, "grid": grid,
+            "step": "log-normal density (sigma 2, clipped to 1e-3..1e4), velocities up to Mach 10, "
+                    "batched step + reduce on the same padded input"}
+
+
 def bench_ctu(tag, state, g, dh, steps, warmup):
     """The CTU-coupled step (three launches through a workspace) on the padded
     groups of the same grid, at the MUSCL-Hancock CFL time step."""
@@ -621,6 +667,8 @@ def main():
             progress(f"{tag}: three-level batch (workload 3)")
             t = res[tag]["tuning"]
             res[tag]["levels_batch"] = bench_levels(tag, max(args.steps // 5, 5), 2, t["variant"], t["grid"])
+            progress(f"{tag}: high-contrast flow (workload 4)")
+            res[tag]["cosmo_batch"] = bench_cosmo(tag, max(args.steps // 5, 5), 2, t["variant"], t["grid"])
     main_tag = "f32" if "f32" in res else "f64"
     m = res[main_tag]
     line = {
