@@ -207,34 +207,43 @@ void solve_kernel(SolveParams<S_> P) {
                 }
             }
         };
-        auto store = [&](int plane) {  // prefetched conserved -> primitive LDS plane
+        // conserved -> primitive, into the LDS slot of a plane
+        auto to_lds = [&](int slot, int pos, const T q[NV]) {
+            const T ir = rcp(q[0]);
+            const T u = q[1] * ir, v = q[2] * ir, w = q[3] * ir;
+            S.w[slot][0][pos] = q[0];
+            S.w[slot][1][pos] = u;
+            S.w[slot][2][pos] = v;
+            S.w[slot][3][pos] = w;
+            S.w[slot][4][pos] = c.gm1 * (q[4] - c.half * q[0] * (u * u + v * v + w * w));
+        };
+        auto store = [&](int plane) {  // the prefetched plane -> its LDS slot
             const int slot = (plane + 3) % 3;
-            {
-                const T ir = rcp(pre0[0]);
-                const T u = pre0[1] * ir, v = pre0[2] * ir, w = pre0[3] * ir;
-                S.w[slot][0][p0] = pre0[0];
-                S.w[slot][1][p0] = u;
-                S.w[slot][2][p0] = v;
-                S.w[slot][3][p0] = w;
-                S.w[slot][4][p0] = c.gm1 * (pre0[4] - c.half * pre0[0] * (u * u + v * v + w * w));
-            }
-            if (has1) {
-                const T ir = rcp(pre1[0]);
-                const T u = pre1[1] * ir, v = pre1[2] * ir, w = pre1[3] * ir;
-                S.w[slot][0][p1] = pre1[0];
-                S.w[slot][1][p1] = u;
-                S.w[slot][2][p1] = v;
-                S.w[slot][3][p1] = w;
-                S.w[slot][4][p1] = c.gm1 * (pre1[4] - c.half * pre1[0] * (u * u + v * v + w * w));
-            }
+            to_lds(slot, p0, pre0);
+            if (has1) to_lds(slot, p1, pre1);
         };
 
-        fetch(-2);
-        store(-2);
-        fetch(-1);
-        store(-1);
-        fetch(0);
-        store(0);
+        // planes -2, -1, 0: every load issued before the first is consumed, so the
+        // group start waits for memory once.  (Threads without a second position
+        // loaded their first one again and write it again: same value, same place.)
+        {
+            T q0[3][NV], q1[3][NV];
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl) {
+                fetch(pl - 2);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    q0[pl][v] = pre0[v];
+                    q1[pl][v] = pre1[v];
+                }
+            }
+#pragma unroll
+            for (int pl = 0; pl < 3; ++pl) {
+                const int slot = (pl + 1) % 3;  // (plane + 3) % 3 of plane pl - 2
+                to_lds(slot, p0, q0[pl]);
+                to_lds(slot, has1 ? p1 : p0, q1[pl]);
+            }
+        }
 
         // carried across sweep steps
         T zp[NV];            // +z state of this column at the previous plane
