@@ -4,8 +4,8 @@
 // relaxing scheme's half step and full step.  The block shrinks by three cells
 // per side along the sweep direction only, so the three sweeps go 22^3 ->
 // 16 x 22 x 22 -> 16 x 16 x 22 -> 16^3 (x, y, z order) through two workspace
-// arrays.  x sweeps: a work-group stages 16 pencils in LDS, so that the loads
-// along x coalesce.  y and z sweeps: one thread per pencil, streaming along it
+// arrays.  x sweeps: a work-group stages 11 pencils in LDS, one lane per
+// position, so that the loads along x coalesce.  y and z sweeps: one thread per pencil, streaming along it
 // in registers, with consecutive threads on consecutive x.
 #include "device_math.h"
 #include "internal.h"
@@ -15,8 +15,8 @@ namespace {
 
 constexpr int RP = 22;      // padded cells per axis (three ghost cells per side)
 constexpr int RG = 3;
-constexpr int PEN = 16;     // pencils per work-group
-constexpr int PSTR = PEN + 1;  // LDS row stride (bank-conflict padding)
+constexpr int XPEN = 11;    // x pencils per work-group, 22 lanes each
+constexpr int XSTR = RP + 1;  // LDS stride per pencil
 
 template <typename T>
 struct SweepArgs {
@@ -34,9 +34,10 @@ struct SweepArgs {
 
 template <typename T>
 struct RtvdLds {
-    T u[NV][RP][PSTR];   // the pencils' input
-    T fr[NV][RP][PSTR];  // c (u + w), then from the half-step state
-    T fl[NV][RP][PSTR];  // c (u - w), likewise
+    T u[NV][XPEN][XSTR];   // the pencils' input
+    T fr[NV][XPEN][XSTR];  // c (u + w), then from the half-step state
+    T fl[NV][XPEN][XSTR];  // c (u - w), likewise
+    T fc[NV][XPEN][XSTR];  // second-order flux of face c0 + 1/2 at index c0
 };
 
 // freezing speed c = |v_d| + c_s and the right/left-moving fluxes
@@ -70,6 +71,12 @@ __device__ __forceinline__ T vanleer(T a, T b) {
     return ab > T(0) ? T(2) * ab * rcp(a + b) : T(0);
 }
 
+// x sweeps: 11 pencils per work-group, one lane per position (22 lanes per
+// pencil, lanes 242..255 idle), positions fastest in LDS.  Each phase is one
+// pass: load, relaxed fluxes of the 22 input cells, half-step state and its
+// relaxed fluxes at positions 1..20, the second-order flux of each of the 17
+// faces once, and the update of the 16 output cells.  Consecutive lanes read
+// consecutive x, so the loads of a wave are contiguous along each pencil.
 template <typename T, bool PERIODIC>
 __global__ __launch_bounds__(256) void rtvd_sweep_kernel(SweepArgs<T> P) {
     __shared__ RtvdLds<T> S;
@@ -79,121 +86,101 @@ __global__ __launch_bounds__(256) void rtvd_sweep_kernel(SweepArgs<T> P) {
     const int tile = int(blockIdx.x) - gi * P.tiles;
     const int64_t g = gi;
     if (g >= P.n_groups) return;
-    const int d = P.d;
-    const int e[3] = {P.ex, P.ey, P.ez};
-    int eo[3] = {P.ex, P.ey, P.ez};
-    eo[d] -= 2 * RG;
-    const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;  // transverse axes, a varies fastest
-    const int npen = e[a] * e[b];
-    const int64_t vin = int64_t(e[0]) * e[1] * e[2], vout = int64_t(eo[0]) * eo[1] * eo[2];
-    // thread <-> (pencil q, position l): positions fastest for x sweeps
-    // (contiguous pencils), pencils fastest otherwise
-    const int q = d == 0 ? (t >> 4) : (t & 15);
-    const int l = d == 0 ? (t & 15) : (t >> 4);
-    const int p = tile * PEN + q;  // pencil index within the group
-    const bool live = p < npen;
-    int idx[3];
-    idx[a] = live ? p % e[a] : 0;
-    idx[b] = live ? p / e[a] : 0;
+    const int ex = P.ex, ey = P.ey, ez = P.ez;  // ex = 22
+    const int eox = ex - 2 * RG;
+    const int64_t vin = int64_t(ex) * ey * ez, vout = int64_t(eox) * ey * ez;
+    const int q = t / RP, l = t - q * RP;  // pencil within the tile, position
+    const int p = tile * XPEN + q;        // pencil index within the group: (y, z), y fastest
+    const bool live = q < XPEN && p < ey * ez;
+    const int iy = live ? p % ey : 0, iz = live ? p / ey : 0;
 
-    int lev = P.level ? int(P.level[g]) : 0;
+    const int lev = P.level ? int(P.level[g]) : 0;
     const double dt = P.dt_dev[lev], dh = P.dh_dev[lev];
     const double dtdx = dt / dh;
     const T g_ = T(P.gamma), gm1 = T(P.gamma - 1.0);
+    const T hdt = T(0.5 * dtdx);
 
-    // ---- load the 16 pencils (positions 0..21) ----
-    for (int s = l; s < RP; s += PEN) {
-        if (!live) break;
-        idx[d] = s;
+    // ---- load position l of pencil q ----
+    if (live) {
         const T *src;
+        int64_t vs;
         if constexpr (PERIODIC) {
             const int bx = gi % P.gx, by = (gi / P.gx) % P.gy, bz = gi / (P.gx * P.gy);
             const int NX = P.gx * NI, NY = P.gy * NI, NZ = P.gz * NI;
-            int X = bx * NI + idx[0] - RG, Y = by * NI + idx[1] - RG, Z = bz * NI + idx[2] - RG;
+            int X = bx * NI + l - RG, Y = by * NI + iy - RG, Z = bz * NI + iz - RG;
             X = X < 0 ? X + NX : (X >= NX ? X - NX : X);
             Y = Y < 0 ? Y + NY : (Y >= NY ? Y - NY : Y);
             Z = Z < 0 ? Z + NZ : (Z >= NZ ? Z - NZ : Z);
             const int64_t grp = X / NI + int64_t(P.gx) * (Y / NI + int64_t(P.gy) * (Z / NI));
             src = P.in + grp * GOUT + ((Z % NI) * NI + (Y % NI)) * NI + (X % NI);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) S.u[v][s][q] = src[v * (NI * NI * NI)];
+            vs = NI * NI * NI;
         } else {
-            src = P.in + g * NV * vin + (int64_t(idx[2]) * e[1] + idx[1]) * e[0] + idx[0];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) S.u[v][s][q] = src[v * vin];
+            src = P.in + g * NV * vin + (int64_t(iz) * ey + iy) * ex + l;
+            vs = vin;
         }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) S.u[v][q][l] = src[v * vs];
     }
     __syncthreads();
 
-    // ---- half step: first-order relaxed fluxes ----
-    for (int s = l; s < RP; s += PEN) {
+    // ---- half step: first-order relaxed fluxes of the input ----
+    if (live) {
         T u[NV], fr[NV], fl[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) u[v] = live ? S.u[v][s][q] : T(1);
-        if (!live) u[4] = T(2);
-        relax(u, d, g_, gm1, fr, fl);
+        for (int v = 0; v < NV; ++v) u[v] = S.u[v][q][l];
+        relax(u, 0, g_, gm1, fr, fl);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            S.fr[v][s][q] = fr[v];
-            S.fl[v][s][q] = fl[v];
+            S.fr[v][q][l] = fr[v];
+            S.fl[v][q][l] = fl[v];
         }
     }
     __syncthreads();
-    // half-step state of positions 1..20, two per lane at most
-    T h[2][NV];
-    const T hdt = T(0.5 * dtdx);
+    // half-step state of positions 1..20
+    const bool hs = live && l >= 1 && l <= RP - 2;
+    T h[NV];
+    if (hs) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int s = 1 + l + r * PEN;
-        if (s <= RP - 2) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const T Fp = T(0.5) * (S.fr[v][s][q] - S.fl[v][s + 1][q]);
-                const T Fm = T(0.5) * (S.fr[v][s - 1][q] - S.fl[v][s][q]);
-                h[r][v] = S.u[v][s][q] - hdt * (Fp - Fm);
-            }
+        for (int v = 0; v < NV; ++v) {
+            const T Fp = T(0.5) * (S.fr[v][q][l] - S.fl[v][q][l + 1]);
+            const T Fm = T(0.5) * (S.fr[v][q][l - 1] - S.fl[v][q][l]);
+            h[v] = S.u[v][q][l] - hdt * (Fp - Fm);
         }
     }
-    __syncthreads();
+    __syncthreads();  // every first-order flux read before it is overwritten
+    if (hs) {
+        T fr[NV], fl[NV];
+        relax(h, 0, g_, gm1, fr, fl);
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int s = 1 + l + r * PEN;
-        if (s <= RP - 2) {
-            T fr[NV], fl[NV];
-            if (!live) {
-#pragma unroll
-                for (int v = 0; v < NV; ++v) h[r][v] = T(1);
-                h[r][4] = T(2);
-            }
-            relax(h[r], d, g_, gm1, fr, fl);
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                S.fr[v][s][q] = fr[v];
-                S.fl[v][s][q] = fl[v];
-            }
+        for (int v = 0; v < NV; ++v) {
+            S.fr[v][q][l] = fr[v];
+            S.fl[v][q][l] = fl[v];
         }
     }
     __syncthreads();
 
-    // ---- full step: second-order fluxes on both faces of cell i = l + 3 ----
-    if (!live) return;
-    const int i = l + RG;
-    idx[d] = l;
-    T *dst = P.out + g * NV * vout + (int64_t(idx[2]) * eo[1] + idx[1]) * eo[0] + idx[0];
+    // ---- full step: the second-order flux of face c0 + 1/2, c0 = l + 2 ----
+    if (live && l <= NI) {
+        const int c0 = l + 2;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        T F[2];
-#pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            const int c0 = i - 1 + f;  // face c0 + 1/2
-            const T r0 = S.fr[v][c0 - 1][q], r1 = S.fr[v][c0][q], r2 = S.fr[v][c0 + 1][q];
-            const T l1 = S.fl[v][c0][q], l2 = S.fl[v][c0 + 1][q], l3 = S.fl[v][c0 + 2][q];
+        for (int v = 0; v < NV; ++v) {
+            const T r0 = S.fr[v][q][c0 - 1], r1 = S.fr[v][q][c0], r2 = S.fr[v][q][c0 + 1];
+            const T l1 = S.fl[v][q][c0], l2 = S.fl[v][q][c0 + 1], l3 = S.fl[v][q][c0 + 2];
             const T R = r1 + vanleer(T(0.5) * (r1 - r0), T(0.5) * (r2 - r1));
             const T L = l2 + vanleer(T(0.5) * (l1 - l2), T(0.5) * (l2 - l3));
-            F[f] = T(0.5) * (R - L);
+            S.fc[v][q][c0] = T(0.5) * (R - L);
         }
-        const double o = double(S.u[v][i][q]) - dtdx * (double(F[1]) - double(F[0]));
-        dst[v * vout] = T(o);
+    }
+    __syncthreads();
+    // update of cell i = l + 3 (output position l)
+    if (live && l < NI) {
+        const int i = l + RG;
+        T *dst = P.out + g * NV * vout + (int64_t(iz) * ey + iy) * eox + l;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double o = double(S.u[v][q][i]) - dtdx * (double(S.fc[v][q][i]) - double(S.fc[v][q][i - 1]));
+            dst[v * vout] = T(o);
+        }
     }
 }
 
@@ -343,7 +330,7 @@ hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int
         P.gamma = gamma;
         P.n_groups = n;
         const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
-        P.tiles = (e[ta] * e[tb] + PEN - 1) / PEN;
+        P.tiles = (e[ta] * e[tb] + XPEN - 1) / XPEN;  // used by the x sweep
         if (d != 0) {
             // y and z pencils: one thread each, streaming (contiguous across the wave)
             if (n * e[ta] * e[tb] >= int64_t(1) << 31) return hipErrorInvalidValue;
@@ -357,7 +344,7 @@ hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int
                 else hipLaunchKernelGGL((rtvd_stream_kernel<T, 2, false>), gr, bl, 0, s, P);
             }
         } else {
-            // x pencils: 16 per work-group through LDS, so that loads along x coalesce
+            // x pencils: 11 per work-group through LDS, so that loads along x coalesce
             const int64_t blocks = n * P.tiles;
             if (blocks > int64_t(1) << 31) return hipErrorInvalidValue;
             if (P.gx > 0)
