@@ -5,10 +5,11 @@
 // keeps its intermediate arrays in a caller-provided workspace and runs as a
 // short pipeline of launches, one stage each:
 //   ctu_zero      clear the per-group fallback counters
-//   ctu_predict   slopes and the one-direction Hancock predictor on the cells
-//                 of [-1,16]^3 with at most two coordinates outside the
-//                 interior (set E1)                          -> Ub [6][5][18^3]
-//                 then the Roe fluxes between neighbouring E1 cells
+//   ctu_predict   one work-group per group sweeping z: slopes and the
+//                 one-direction Hancock predictor on the cells of [-1,16]^3
+//                 with at most two coordinates outside the interior (set E1),
+//                 primitive planes in an LDS ring            -> Ub [6][5][18^3]
+//                 and the Roe fluxes between neighbouring E1 cells
 //                                                            -> Ft [3][5][18^3]
 //   ctu_final     one work-group per group sweeping z: corrected states and the
 //                 final Roe fluxes of each plane (x and y faces through LDS, z
@@ -85,15 +86,14 @@ __device__ __forceinline__ void prim_at(const T *U, int i, int j, int k, const C
     w[4] = c.gm1 * (U[o + 4 * NP * NP * NP] - c.half * r * (u * u + v * v + wz * wz));
 }
 
+// One-direction Hancock predictor of a cell along D, from its primitive state
+// W0 and those of its two neighbours along D: the limited slope, the face
+// values W0 -+ dW/2, and their conserved states advanced by dt/(2dh) times the
+// flux difference along D.  False if either state is unphysical.
 template <int D, typename T>
-__device__ __forceinline__ bool predict_dir(const T *U, int i, int j, int k, const T W0[NV], T hdt,
-                                            const Consts<T> &c, T um[NV], T up[NV]) {
-    int im = i, jm = j, km = k, iq = i, jq = j, kq = k;
-    nb<D>(-1, im, jm, km);
-    nb<D>(+1, iq, jq, kq);
-    T wl[NV], wr[NV], wm[NV], wp[NV], fm[NV], fp[NV];
-    prim_at(U, im, jm, km, c, wl);
-    prim_at(U, iq, jq, kq, c, wr);
+__device__ __forceinline__ bool predict_from(const T W0[NV], const T wl[NV], const T wr[NV], T hdt,
+                                             const Consts<T> &c, T um[NV], T up[NV]) {
+    T wm[NV], wp[NV], fm[NV], fp[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const T dw = limiter(W0[v] - wl[v], wr[v] - W0[v], c.theta);
@@ -113,18 +113,27 @@ __device__ __forceinline__ bool predict_dir(const T *U, int i, int j, int k, con
     return physical(um) && physical(up);
 }
 
-// blocks: n * 18, one plane k = -1..16 of one group each; threads loop over the
-// 18 x 18 cells.  First the predicted states of the plane's E1 cells (the
-// one-direction Hancock predictor, per direction) -> Ub; then, after a barrier,
-// the transverse Roe fluxes at the faces c + e_d/2 between two E1 cells whose
-// lower cell lies in the plane -> Ft.  The x and y faces read both states from
-// Ub as this work-group wrote them; for the z face the minus-z state of the
-// cell above, which the next plane's work-group writes, is recomputed here (the
-// same function on the same inputs, so the same value).
+template <typename T>
+struct PredLds {
+    T w[3][NV][NP][NP];  // primitive states of padded planes: plane m in slot (m + 3) % 3
+    T xm[NV][CE][CE];    // minus-x predicted state of the plane's E1 cells, at [v][j + 1][i + 1]
+    T ym[NV][CE][CE];    // minus-y, likewise
+};
+
+// One work-group of 256 threads per group, sweeping k = -1..16.  Thread t owns
+// the cell at position t of the 18 x 18 plane, and threads 0..67 also the one
+// at position 256 + t.  At step k: the primitive states of padded plane k + 1
+// into the LDS ring (planes k - 1 and k are there from the previous steps);
+// after a barrier, the predicted states of the plane's E1 cells (the
+// one-direction Hancock predictor, per direction) -> Ub, their minus-x and
+// minus-y states also to LDS, and the transverse z flux between the cell below,
+// whose plus-z state this thread kept from the previous step, and the cell
+// -> Ft; after a second barrier, the transverse x and y fluxes of the plane
+// from each cell's plus states and its neighbours' minus states -> Ft.
 template <typename T>
 __global__ __launch_bounds__(256) void ctu_predict(CtuArgs<T> P) {
-    const int64_t g = blockIdx.x / CE;
-    const int k = int(blockIdx.x % CE) - 1;
+    __shared__ PredLds<T> S;
+    const int64_t g = blockIdx.x;
     if (g >= P.n_groups) return;
     const Consts<T> c = make_consts<T>(P.gamma, P.theta);
     double dt, dh;
@@ -133,65 +142,111 @@ __global__ __launch_bounds__(256) void ctu_predict(CtuArgs<T> P) {
     const T *U = P.in + g * GIN;
     T *Ub = P.work + g * WORK_VALUES;
     T *Ft = Ub + UB_VALUES;
+    const int t = threadIdx.x;
+    const bool two = t < CE * CE - 256;  // owns a second cell
+    int ci[2], cj[2];
+    ci[0] = t % CE - 1;
+    cj[0] = t / CE - 1;
+    ci[1] = (256 + t) % CE - 1;
+    cj[1] = (256 + t) / CE - 1;
     int bad = 0, bad_roe = 0;
-    for (int q = threadIdx.x; q < CE * CE; q += 256) {
-        const int i = q % CE - 1, j = q / CE - 1;
-        if (!in_e1(i, j, k)) continue;
-        T W0[NV];
-        prim_at(U, i, j, k, c, W0);
-        const int e = eidx(i, j, k);
-        const int o = ((k + NG) * NP + (j + NG)) * NP + (i + NG);
+    T zp[2][NV];  // plus-z predicted state of each owned cell in the plane below
+
+    // primitive states of padded plane m (-2..17) into its slot of the ring
+    auto fill = [&](int m) {
+        const int slot = (m + 3) % 3;
+        for (int q = t; q < NPL; q += 256) {
+            const int ii = q % NP, jj = q / NP;
+            T w[NV];
+            prim_at(U, ii - NG, jj - NG, m, c, w);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            T um[NV], up[NV];
-            const bool ok = d == 0   ? predict_dir<0>(U, i, j, k, W0, hdt, c, um, up)
-                            : d == 1 ? predict_dir<1>(U, i, j, k, W0, hdt, c, um, up)
-                                     : predict_dir<2>(U, i, j, k, W0, hdt, c, um, up);
-            if (!ok) {
-                ++bad;
-#pragma unroll
-                for (int v = 0; v < NV; ++v) um[v] = up[v] = U[o + v * NP * NP * NP];
-            }
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                Ub[((2 * d + 0) * NV + v) * E3 + e] = um[v];
-                Ub[((2 * d + 1) * NV + v) * E3 + e] = up[v];
-            }
+            for (int v = 0; v < NV; ++v) S.w[slot][v][jj][ii] = w[v];
         }
-    }
-    __syncthreads();  // the plane's predicted states visible to the whole work-group
-    for (int q = threadIdx.x; q < CE * CE; q += 256) {
-        const int i = q % CE - 1, j = q / CE - 1;
-        if (!in_e1(i, j, k)) continue;
-        const int e = eidx(i, j, k);
+    };
+    fill(-2);
+    fill(-1);
+    for (int k = -1; k <= NI; ++k) {
+        fill(k + 1);
+        __syncthreads();  // planes k - 1, k and k + 1 in LDS
+        const int sm = (k + 2) % 3, s0 = (k + 3) % 3, sp = (k + 4) % 3;
+        T xp[2][NV], yp[2][NV];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            int iq = i, jq = j, kq = k;
-            if (d == 0) ++iq;
-            if (d == 1) ++jq;
-            if (d == 2) ++kq;
-            if (!in_e1(iq, jq, kq)) continue;
-            T L[NV], R[NV], F[NV];
+        for (int r = 0; r < 2; ++r) {
+            const int i = ci[r], j = cj[r];
+            if ((r == 1 && !two) || !in_e1(i, j, k)) continue;
+            const int ii = i + NG, jj = j + NG;
+            const int e = eidx(i, j, k);
+            const int o = ((k + NG) * NP + jj) * NP + ii;
+            T W0[NV], wl[NV], wr[NV], um[NV], up[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) L[v] = Ub[((2 * d + 1) * NV + v) * E3 + e];
-            if (d < 2) {
-                const int eq = eidx(iq, jq, kq);
+            for (int v = 0; v < NV; ++v) W0[v] = S.w[s0][v][jj][ii];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) R[v] = Ub[((2 * d + 0) * NV + v) * E3 + eq];
-            } else {  // minus-z state of the cell above
-                T Wq[NV], up[NV];
-                prim_at(U, iq, jq, kq, c, Wq);
-                if (!predict_dir<2>(U, iq, jq, kq, Wq, hdt, c, R, up)) {
-                    const int oq = ((kq + NG) * NP + (jq + NG)) * NP + (iq + NG);
+            for (int d = 0; d < 3; ++d) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) R[v] = U[oq + v * NP * NP * NP];
+                for (int v = 0; v < NV; ++v) {
+                    wl[v] = d == 0 ? S.w[s0][v][jj][ii - 1] : d == 1 ? S.w[s0][v][jj - 1][ii] : S.w[sm][v][jj][ii];
+                    wr[v] = d == 0 ? S.w[s0][v][jj][ii + 1] : d == 1 ? S.w[s0][v][jj + 1][ii] : S.w[sp][v][jj][ii];
+                }
+                const bool ok = d == 0   ? predict_from<0>(W0, wl, wr, hdt, c, um, up)
+                                : d == 1 ? predict_from<1>(W0, wl, wr, hdt, c, um, up)
+                                         : predict_from<2>(W0, wl, wr, hdt, c, um, up);
+                if (!ok) {
+                    ++bad;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) um[v] = up[v] = U[o + v * NP * NP * NP];
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    Ub[((2 * d + 0) * NV + v) * E3 + e] = um[v];
+                    Ub[((2 * d + 1) * NV + v) * E3 + e] = up[v];
+                }
+                if (d == 0) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        S.xm[v][j + 1][i + 1] = um[v];
+                        xp[r][v] = up[v];
+                    }
+                } else if (d == 1) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        S.ym[v][j + 1][i + 1] = um[v];
+                        yp[r][v] = up[v];
+                    }
+                } else {
+                    // transverse z flux at the face between the cell below and this one
+                    if (k >= 0 && in_e1(i, j, k - 1)) {
+                        T F[NV];
+                        bad_roe += roe_dir<2>(zp[r], um, c, F);
+                        const int eb = eidx(i, j, k - 1);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) Ft[(2 * NV + v) * E3 + eb] = F[v];
+                    }
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) zp[r][v] = up[v];
                 }
             }
-            const bool fb = d == 0 ? roe_dir<0>(L, R, c, F) : d == 1 ? roe_dir<1>(L, R, c, F)
-                                                                    : roe_dir<2>(L, R, c, F);
-            bad_roe += fb;
+        }
+        __syncthreads();  // the plane's minus-x and minus-y states visible
 #pragma unroll
-            for (int v = 0; v < NV; ++v) Ft[(d * NV + v) * E3 + e] = F[v];
+        for (int r = 0; r < 2; ++r) {
+            const int i = ci[r], j = cj[r];
+            if ((r == 1 && !two) || !in_e1(i, j, k)) continue;
+            const int e = eidx(i, j, k);
+            T R[NV], F[NV];
+            if (in_e1(i + 1, j, k)) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) R[v] = S.xm[v][j + 1][i + 2];
+                bad_roe += roe_dir<0>(xp[r], R, c, F);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Ft[(0 * NV + v) * E3 + e] = F[v];
+            }
+            if (in_e1(i, j + 1, k)) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) R[v] = S.ym[v][j + 2][i + 1];
+                bad_roe += roe_dir<1>(yp[r], R, c, F);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) Ft[(1 * NV + v) * E3 + e] = F[v];
+            }
         }
     }
     if (bad) atomicAdd(P.counts + 2 * g, bad);
@@ -378,7 +433,7 @@ hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double 
     const size_t off = (size_t(n) * size_t(WORK_VALUES) * sizeof(T) + 255) & ~size_t(255);
     P.counts = reinterpret_cast<int *>(static_cast<char *>(work) + off);
     hipLaunchKernelGGL(ctu_zero<T>, dim3(unsigned((2 * n + 255) / 256)), dim3(256), 0, s, P);
-    hipLaunchKernelGGL(ctu_predict<T>, dim3(unsigned(n * CE)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(ctu_predict<T>, dim3(unsigned(n)), dim3(256), 0, s, P);
     hipLaunchKernelGGL(ctu_final<T>, dim3(unsigned(n)), dim3(256), 0, s, P);
     return hipGetLastError();
 }
