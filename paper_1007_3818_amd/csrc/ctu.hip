@@ -120,9 +120,16 @@ struct PredLds {
     T ym[NV][CE][CE];    // minus-y, likewise
 };
 
-// One work-group of 256 threads per group, sweeping k = -1..16.  Thread t owns
-// the cell at position t of the 18 x 18 plane, and threads 0..67 also the one
-// at position 256 + t.  At step k: the primitive states of padded plane k + 1
+// Work-group size of the predictor: 384 threads in float, one E1 cell of a
+// plane each (the 324 positions of the 18 x 18 square); 256 in double, where
+// the registers allow only two waves per SIMD and threads 0..67 take a second
+// cell.
+template <typename T>
+constexpr int pred_threads() { return sizeof(T) == 4 ? 384 : 256; }
+
+// One work-group per group, sweeping k = -1..16.  Thread t owns the cell at
+// position t of the 18 x 18 plane (and, with 256 threads, threads 0..67 also
+// the one at position 256 + t).  At step k: the primitive states of padded plane k + 1
 // into the LDS ring (planes k - 1 and k are there from the previous steps);
 // after a barrier, the predicted states of the plane's E1 cells (the
 // one-direction Hancock predictor, per direction) -> Ub, their minus-x and
@@ -131,7 +138,7 @@ struct PredLds {
 // -> Ft; after a second barrier, the transverse x and y fluxes of the plane
 // from each cell's plus states and its neighbours' minus states -> Ft.
 template <typename T>
-__global__ __launch_bounds__(256) void ctu_predict(CtuArgs<T> P) {
+__global__ __launch_bounds__(pred_threads<T>()) void ctu_predict(CtuArgs<T> P) {
     __shared__ PredLds<T> S;
     const int64_t g = blockIdx.x;
     if (g >= P.n_groups) return;
@@ -142,20 +149,22 @@ __global__ __launch_bounds__(256) void ctu_predict(CtuArgs<T> P) {
     const T *U = P.in + g * GIN;
     T *Ub = P.work + g * WORK_VALUES;
     T *Ft = Ub + UB_VALUES;
+    constexpr int NT = pred_threads<T>();
     const int t = threadIdx.x;
-    const bool two = t < CE * CE - 256;  // owns a second cell
+    const bool one = t < CE * CE;             // owns a first cell
+    const bool two = t + NT < CE * CE;        // owns a second cell
     int ci[2], cj[2];
     ci[0] = t % CE - 1;
     cj[0] = t / CE - 1;
-    ci[1] = (256 + t) % CE - 1;
-    cj[1] = (256 + t) / CE - 1;
+    ci[1] = (NT + t) % CE - 1;
+    cj[1] = (NT + t) / CE - 1;
     int bad = 0, bad_roe = 0;
     T zp[2][NV];  // plus-z predicted state of each owned cell in the plane below
 
     // primitive states of padded plane m (-2..17) into its slot of the ring
     auto fill = [&](int m) {
         const int slot = (m + 3) % 3;
-        for (int q = t; q < NPL; q += 256) {
+        for (int q = t; q < NPL; q += NT) {
             const int ii = q % NP, jj = q / NP;
             T w[NV];
             prim_at(U, ii - NG, jj - NG, m, c, w);
@@ -173,7 +182,7 @@ __global__ __launch_bounds__(256) void ctu_predict(CtuArgs<T> P) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int i = ci[r], j = cj[r];
-            if ((r == 1 && !two) || !in_e1(i, j, k)) continue;
+            if (!(r == 0 ? one : two) || !in_e1(i, j, k)) continue;
             const int ii = i + NG, jj = j + NG;
             const int e = eidx(i, j, k);
             const int o = ((k + NG) * NP + jj) * NP + ii;
@@ -230,7 +239,7 @@ __global__ __launch_bounds__(256) void ctu_predict(CtuArgs<T> P) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int i = ci[r], j = cj[r];
-            if ((r == 1 && !two) || !in_e1(i, j, k)) continue;
+            if (!(r == 0 ? one : two) || !in_e1(i, j, k)) continue;
             const int e = eidx(i, j, k);
             T R[NV], F[NV];
             if (in_e1(i + 1, j, k)) {
@@ -433,7 +442,7 @@ hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double 
     const size_t off = (size_t(n) * size_t(WORK_VALUES) * sizeof(T) + 255) & ~size_t(255);
     P.counts = reinterpret_cast<int *>(static_cast<char *>(work) + off);
     hipLaunchKernelGGL(ctu_zero<T>, dim3(unsigned((2 * n + 255) / 256)), dim3(256), 0, s, P);
-    hipLaunchKernelGGL(ctu_predict<T>, dim3(unsigned(n)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(ctu_predict<T>, dim3(unsigned(n)), dim3(pred_threads<T>()), 0, s, P);
     hipLaunchKernelGGL(ctu_final<T>, dim3(unsigned(n)), dim3(256), 0, s, P);
     return hipGetLastError();
 }
