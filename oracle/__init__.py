@@ -337,6 +337,27 @@ def pack_periodic_rtvd(state, gx, gy, gz):
     return out
 
 
+def pack_periodic_rtvd_subset(state, gx, gy, gz, ids):
+    """Padded groups (len(ids), 5, 22, 22, 22) with three ghost cells per side
+    for the listed groups of a periodic grid, assembled from the 3 x 3 x 3
+    neighbourhood of each group.  ``state`` as in pack_periodic_subset."""
+    out = np.empty((len(ids), 5, 22, 22, 22))
+    for n, g in enumerate(ids):
+        g = int(g)
+        bx, by, bz = g % gx, (g // gx) % gy, g // (gx * gy)
+        block = np.empty((5, 48, 48, 48))
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    nb = ((bx + dx) % gx) + gx * (((by + dy) % gy) + gy * ((bz + dz) % gz))
+                    q = state[nb]
+                    q = q.detach().cpu().double().numpy() if hasattr(q, "detach") else np.asarray(q, np.float64)
+                    block[:, 16 * (dz + 1):16 * (dz + 2), 16 * (dy + 1):16 * (dy + 2),
+                          16 * (dx + 1):16 * (dx + 2)] = q
+        out[n] = block[:, 16 - RG:32 + RG, 16 - RG:32 + RG, 16 - RG:32 + RG]
+    return out
+
+
 def rtvd_step_periodic(state, gx, gy, gz, dt, dh, gamma, order=0):
     out, bad = rtvd_solve(pack_periodic_rtvd(state, gx, gy, gz), dt, dh, gamma, order)
     return out, bad

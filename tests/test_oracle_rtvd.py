@@ -84,6 +84,11 @@ def test_pack_rtvd_brute_force():
         bx, by, bz = g % gx, (g // gx) % gy, g // (gx * gy)
         X, Y, Z = (16 * bx + i) % (16 * gx), (16 * by + j) % (16 * gy), (16 * bz + k) % (16 * gz)
         assert np.array_equal(pad[g, :, k + 3, j + 3, i + 3], G[:, Z, Y, X])
+    # the subset pack (sampled full-size tests) gives the same padded groups,
+    # from numpy or torch input
+    ids = [0, 5, 11, 7]
+    assert np.array_equal(oracle.pack_periodic_rtvd_subset(st, gx, gy, gz, ids), pad[ids])
+    assert np.array_equal(oracle.pack_periodic_rtvd_subset(torch.from_numpy(st), gx, gy, gz, ids), pad[ids])
 
 
 def test_conservation_periodic():
