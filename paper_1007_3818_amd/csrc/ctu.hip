@@ -120,16 +120,16 @@ struct PredLds {
     T ym[NV][CE][CE];    // minus-y, likewise
 };
 
-// Work-group size of the predictor: 384 threads in float, one E1 cell of a
-// plane each (the 324 positions of the 18 x 18 square); 256 in double, where
-// the registers allow only two waves per SIMD and threads 0..67 take a second
-// cell.
+// Work-group size of the predictor, one E1 cell of a plane per thread (the
+// 324 positions of the 18 x 18 square): 384 threads in float (three
+// work-groups per CU); 512 in double, whose registers allow two waves per
+// SIMD, so that one work-group fills the CU and every phase is one pass.
 template <typename T>
-constexpr int pred_threads() { return sizeof(T) == 4 ? 384 : 256; }
+constexpr int pred_threads() { return sizeof(T) == 4 ? 384 : 512; }
 
 // One work-group per group, sweeping k = -1..16.  Thread t owns the cell at
-// position t of the 18 x 18 plane (and, with 256 threads, threads 0..67 also
-// the one at position 256 + t).  At step k: the primitive states of padded plane k + 1
+// position t of the 18 x 18 plane (with fewer than 324 threads, thread t also
+// owns the one at position NT + t).  At step k: the primitive states of padded plane k + 1
 // into the LDS ring (planes k - 1 and k are there from the previous steps);
 // after a barrier, the predicted states of the plane's E1 cells (the
 // one-direction Hancock predictor, per direction) -> Ub, their minus-x and
