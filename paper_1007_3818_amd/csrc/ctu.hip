@@ -127,18 +127,19 @@ struct PredLds {
 template <typename T>
 constexpr int pred_threads() { return sizeof(T) == 4 ? 384 : 512; }
 
-// One work-group per group, sweeping k = -1..16.  Thread t owns the cell at
-// position t of the 18 x 18 plane (with fewer than 324 threads, thread t also
-// owns the one at position NT + t).  At step k: the primitive states of padded plane k + 1
-// into the LDS ring (planes k - 1 and k are there from the previous steps);
-// after a barrier, the predicted states of the plane's E1 cells (the
-// one-direction Hancock predictor, per direction) -> Ub, their minus-x and
-// minus-y states also to LDS, and the transverse z flux between the cell below,
-// whose plus-z state this thread kept from the previous step, and the cell
-// -> Ft; after a second barrier, the transverse x and y fluxes of the plane
-// from each cell's plus states and its neighbours' minus states -> Ft.
+// One work-group per group, sweeping k = -1..16; thread t < 324 owns the cell
+// at position t of the 18 x 18 plane.  At step k: the primitive states of
+// padded plane k + 1 into the LDS ring (planes k - 1 and k are there from the
+// previous steps); after a barrier, the predicted states of the plane's E1
+// cells (the one-direction Hancock predictor, per direction) -> Ub, their
+// minus-x and minus-y states also to LDS, and the transverse z flux between the
+// cell below, whose plus-z state this thread kept from the previous step, and
+// the cell -> Ft; after a second barrier, the transverse x and y fluxes of the
+// plane from each cell's plus states and its neighbours' minus states -> Ft.
 template <typename T>
 __global__ __launch_bounds__(pred_threads<T>()) void ctu_predict(CtuArgs<T> P) {
+    constexpr int NT = pred_threads<T>();
+    static_assert(NT >= CE * CE, "one thread per cell of a plane");
     __shared__ PredLds<T> S;
     const int64_t g = blockIdx.x;
     if (g >= P.n_groups) return;
@@ -149,27 +150,21 @@ __global__ __launch_bounds__(pred_threads<T>()) void ctu_predict(CtuArgs<T> P) {
     const T *U = P.in + g * GIN;
     T *Ub = P.work + g * WORK_VALUES;
     T *Ft = Ub + UB_VALUES;
-    constexpr int NT = pred_threads<T>();
     const int t = threadIdx.x;
-    const bool one = t < CE * CE;             // owns a first cell
-    const bool two = t + NT < CE * CE;        // owns a second cell
-    int ci[2], cj[2];
-    ci[0] = t % CE - 1;
-    cj[0] = t / CE - 1;
-    ci[1] = (NT + t) % CE - 1;
-    cj[1] = (NT + t) / CE - 1;
+    const int i = t % CE - 1, j = t / CE - 1;  // meaningful for t < 324 only
+    const int ii = i + NG, jj = j + NG;
     int bad = 0, bad_roe = 0;
-    T zp[2][NV];  // plus-z predicted state of each owned cell in the plane below
+    T zp[NV];  // plus-z predicted state of this thread's cell in the plane below
 
     // primitive states of padded plane m (-2..17) into its slot of the ring
     auto fill = [&](int m) {
         const int slot = (m + 3) % 3;
         for (int q = t; q < NPL; q += NT) {
-            const int ii = q % NP, jj = q / NP;
+            const int qi = q % NP, qj = q / NP;
             T w[NV];
-            prim_at(U, ii - NG, jj - NG, m, c, w);
+            prim_at(U, qi - NG, qj - NG, m, c, w);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) S.w[slot][v][jj][ii] = w[v];
+            for (int v = 0; v < NV; ++v) S.w[slot][v][qj][qi] = w[v];
         }
     };
     fill(-2);
@@ -178,12 +173,9 @@ __global__ __launch_bounds__(pred_threads<T>()) void ctu_predict(CtuArgs<T> P) {
         fill(k + 1);
         __syncthreads();  // planes k - 1, k and k + 1 in LDS
         const int sm = (k + 2) % 3, s0 = (k + 3) % 3, sp = (k + 4) % 3;
-        T xp[2][NV], yp[2][NV];
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int i = ci[r], j = cj[r];
-            if (!(r == 0 ? one : two) || !in_e1(i, j, k)) continue;
-            const int ii = i + NG, jj = j + NG;
+        const bool mine = t < CE * CE && in_e1(i, j, k);
+        T xp[NV], yp[NV];
+        if (mine) {
             const int e = eidx(i, j, k);
             const int o = ((k + NG) * NP + jj) * NP + ii;
             T W0[NV], wl[NV], wr[NV], um[NV], up[NV];
@@ -213,46 +205,43 @@ __global__ __launch_bounds__(pred_threads<T>()) void ctu_predict(CtuArgs<T> P) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         S.xm[v][j + 1][i + 1] = um[v];
-                        xp[r][v] = up[v];
+                        xp[v] = up[v];
                     }
                 } else if (d == 1) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         S.ym[v][j + 1][i + 1] = um[v];
-                        yp[r][v] = up[v];
+                        yp[v] = up[v];
                     }
                 } else {
                     // transverse z flux at the face between the cell below and this one
                     if (k >= 0 && in_e1(i, j, k - 1)) {
                         T F[NV];
-                        bad_roe += roe_dir<2>(zp[r], um, c, F);
+                        bad_roe += roe_dir<2>(zp, um, c, F);
                         const int eb = eidx(i, j, k - 1);
 #pragma unroll
                         for (int v = 0; v < NV; ++v) Ft[(2 * NV + v) * E3 + eb] = F[v];
                     }
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) zp[r][v] = up[v];
+                    for (int v = 0; v < NV; ++v) zp[v] = up[v];
                 }
             }
         }
         __syncthreads();  // the plane's minus-x and minus-y states visible
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int i = ci[r], j = cj[r];
-            if (!(r == 0 ? one : two) || !in_e1(i, j, k)) continue;
+        if (mine) {
             const int e = eidx(i, j, k);
             T R[NV], F[NV];
             if (in_e1(i + 1, j, k)) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) R[v] = S.xm[v][j + 1][i + 2];
-                bad_roe += roe_dir<0>(xp[r], R, c, F);
+                bad_roe += roe_dir<0>(xp, R, c, F);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) Ft[(0 * NV + v) * E3 + e] = F[v];
             }
             if (in_e1(i, j + 1, k)) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) R[v] = S.ym[v][j + 2][i + 1];
-                bad_roe += roe_dir<1>(yp[r], R, c, F);
+                bad_roe += roe_dir<1>(yp, R, c, F);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) Ft[(1 * NV + v) * E3 + e] = F[v];
             }
