@@ -121,11 +121,10 @@ struct PredLds {
 };
 
 // Work-group size of the predictor, one E1 cell of a plane per thread (the
-// 324 positions of the 18 x 18 square): 384 threads in float (three
-// work-groups per CU); 512 in double, whose registers allow two waves per
-// SIMD, so that one work-group fills the CU and every phase is one pass.
-template <typename T>
-constexpr int pred_threads() { return sizeof(T) == 4 ? 384 : 512; }
+// 324 positions of the 18 x 18 square), so that every phase is one pass: in
+// double (156 VGPRs, two waves per SIMD) one work-group fills the CU; in float
+// (86 VGPRs) three do.
+constexpr int PRED_THREADS = 512;
 
 // One work-group per group, sweeping k = -1..16; thread t < 324 owns the cell
 // at position t of the 18 x 18 plane.  At step k: the primitive states of
@@ -137,8 +136,8 @@ constexpr int pred_threads() { return sizeof(T) == 4 ? 384 : 512; }
 // the cell -> Ft; after a second barrier, the transverse x and y fluxes of the
 // plane from each cell's plus states and its neighbours' minus states -> Ft.
 template <typename T>
-__global__ __launch_bounds__(pred_threads<T>()) void ctu_predict(CtuArgs<T> P) {
-    constexpr int NT = pred_threads<T>();
+__global__ __launch_bounds__(PRED_THREADS) void ctu_predict(CtuArgs<T> P) {
+    constexpr int NT = PRED_THREADS;
     static_assert(NT >= CE * CE, "one thread per cell of a plane");
     __shared__ PredLds<T> S;
     const int64_t g = blockIdx.x;
@@ -431,7 +430,7 @@ hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double 
     const size_t off = (size_t(n) * size_t(WORK_VALUES) * sizeof(T) + 255) & ~size_t(255);
     P.counts = reinterpret_cast<int *>(static_cast<char *>(work) + off);
     hipLaunchKernelGGL(ctu_zero<T>, dim3(unsigned((2 * n + 255) / 256)), dim3(256), 0, s, P);
-    hipLaunchKernelGGL(ctu_predict<T>, dim3(unsigned(n)), dim3(pred_threads<T>()), 0, s, P);
+    hipLaunchKernelGGL(ctu_predict<T>, dim3(unsigned(n)), dim3(PRED_THREADS), 0, s, P);
     hipLaunchKernelGGL(ctu_final<T>, dim3(unsigned(n)), dim3(256), 0, s, P);
     return hipGetLastError();
 }
