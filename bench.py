@@ -619,8 +619,8 @@ def main():
     ap.add_argument("--grid", type=int, default=0, help="launch grid with --variant (0: one per group)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
-                                   "note, not an implemented path", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the solver runs on one GPU only; sharding across GPUs is "
+                                   "described, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
