@@ -123,7 +123,7 @@ struct PredLds {
 // Work-group size of the predictor, one E1 cell of a plane per thread (the
 // 324 positions of the 18 x 18 square), so that every phase is one pass: in
 // double (156 VGPRs, two waves per SIMD) one work-group fills the CU; in float
-// (86 VGPRs) three do.
+// (86 VGPRs) two fit.
 constexpr int PRED_THREADS = 512;
 
 // One work-group per group, sweeping k = -1..16; thread t < 324 owns the cell
