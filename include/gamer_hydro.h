@@ -28,7 +28,9 @@
  *      group stats     [n][8] doubles: sum rho, sum m_x, sum m_y, sum m_z,
  *                      sum E over the 16^3 output cells (not multiplied by
  *                      dh^3), max over output cells of |u|+|v|+|w|+3 c_s
- *                      (evaluated in the working precision),
+ *                      (evaluated in the working precision; NaN if any
+ *                      output cell has rho <= 0, p <= 0 or a non-finite
+ *                      value, since such a state has no sound speed),
  *                      number of cells whose half-step prediction fell back
  *                      to first order, number of faces whose Roe flux fell
  *                      back to HLLE.
@@ -85,6 +87,17 @@ typedef struct gamer_opts {
      * choices of the MUSCL-Hancock reconstruction step, Toro 2009, Sec. 14). */
     int32_t limiting;
     int32_t reserved; /* must be 0 */
+    /* Two device counters the step adds to, or NULL (8-byte aligned device
+     * memory, zeroed by the caller; accumulated with atomics, so their order of
+     * arrival is free but the totals are exact):
+     *   bad_count_dev[0] += updated cells that are not physical (rho <= 0 or
+     *                       p <= 0) or not finite;
+     *   bad_count_dev[1] += groups whose level byte lies outside [0, n_levels).
+     * Such cells are not errors of the call (see the conventions above).  The
+     * positivity reading: the method keeps states physical through its two
+     * fallbacks; a cell that still leaves the physical set is reported, never
+     * clipped, so the stored state stays conservative. */
+    uint64_t *bad_count_dev;
 } gamer_opts;
 
 #define GAMER_LIMIT_PRIMITIVE 0
@@ -130,17 +143,22 @@ int gamer_hydro_solve_f32(const float *groups_in, int64_t n_groups, double dt, d
  * read ON THE DEVICE: group g uses dt_dev[level[g]] and dh_dev[level[g]]
  * (level == NULL: every group uses level 0), so a captured HIP graph can be
  * replayed while dt changes.  level: device int8 [n_groups], values in
- * 0..n_levels-1 (not checked on the device).  dt_dev, dh_dev: device double
+ * 0..n_levels-1.  The device checks every level byte: a group whose level
+ * lies outside [0, n_levels) never indexes dt_dev or dh_dev; it is advanced
+ * with NaN dt and dh, so its output block and stats row come out NaN, and it
+ * is counted in opts->bad_count_dev[1].  dt_dev, dh_dev: device double
  * [n_levels], 1 <= n_levels <= GAMER_MAX_LEVELS.  group_stats: device double
- * [n_groups][8] (see conventions) or NULL.  opts may be NULL. */
+ * [n_groups][8] (see conventions) or NULL.  opts may be NULL.  hip_stream: the
+ * hipStream_t to launch on, or NULL for the calling thread's current stream
+ * (gamer_set_stream). */
 int gamer_hydro_solve_batched(const double *groups_in, int64_t n_groups, const int8_t *level,
                               const double *dt_dev, const double *dh_dev, int n_levels,
                               double gamma, double *fluxes_out, double *groups_out,
-                              double *group_stats, const gamer_opts *opts);
+                              double *group_stats, const gamer_opts *opts, void *hip_stream);
 int gamer_hydro_solve_batched_f32(const float *groups_in, int64_t n_groups, const int8_t *level,
                                   const double *dt_dev, const double *dh_dev, int n_levels,
                                   double gamma, float *fluxes_out, float *groups_out,
-                                  double *group_stats, const gamer_opts *opts);
+                                  double *group_stats, const gamer_opts *opts, void *hip_stream);
 
 /* ---- one step of a uniform periodic grid, ghost cells fetched in place ---
  * The same step as gamer_hydro_solve_batched, for the interior state of a
@@ -175,7 +193,7 @@ int gamer_hydro_solve_periodic_f32(const float *state, int gx, int gy, int gz, c
 int gamer_hydro_solve_batched_mixed(const double *groups_in, int64_t n_groups, const int8_t *level,
                                     const double *dt_dev, const double *dh_dev, int n_levels,
                                     double gamma, double *fluxes_out, double *groups_out,
-                                    double *group_stats, const gamer_opts *opts);
+                                    double *group_stats, const gamer_opts *opts, void *hip_stream);
 int gamer_hydro_solve_periodic_mixed(const double *state, int gx, int gy, int gz,
                                      const double *dt_dev, const double *dh_dev, double gamma,
                                      double *fluxes_out, double *state_out, double *group_stats,
@@ -186,9 +204,13 @@ int gamer_hydro_solve_periodic_mixed(const double *state, int gx, int gy, int gz
  * gamer_group_stats), computes on the device, in a fixed order (results are
  * bitwise reproducible):
  *   dt_dev_out[L] = cfl * dh_dev[L] / max over groups of level L of stat 5
- *                   (+inf when level L has no group or a zero maximum);
+ *                   (+inf when level L has no group or a zero maximum; NaN
+ *                   when a group of level L has a NaN stat 5, i.e. holds a
+ *                   cell that is not physical);
  *   totals_dev_out[0..4] = sum over groups of dh_dev[level]^3 * stats 0..4,
  *   totals_dev_out[5..6] = sum over groups of stats 6..7.
+ * A group whose level lies outside [0, n_levels) is read with no index into
+ * dh_dev: it belongs to no level's dt and makes totals 0..4 NaN.
  * Either output may be NULL.  level, dh_dev, n_levels as in the batched step.
  * Errors: GAMER_EINVAL for cfl not finite and positive, bad sizes. */
 int gamer_step_reduce(const double *group_stats, int64_t n_groups, const int8_t *level,
@@ -204,7 +226,8 @@ int gamer_group_stats_f32(const float *groups, int64_t n_groups, double gamma,
 /* ---- CFL time step ------------------------------------------------------
  * dt = cfl * dh / max over all interior cells of (|u| + |v| + |w| + 3 c_s), the
  * 3D unsplit stability bound (the paper does not state its CFL form),
- * evaluated in the working precision (the _f32 variant in float).
+ * evaluated in the working precision (the _f32 variant in float).  NaN when
+ * a cell is not physical (rho <= 0 or p <= 0) or not finite.
  * groups: interior [n][5][16][16][16].  dt_out is a device pointer when
  * dt_out_is_device != 0 (asynchronous), else a host pointer (the call then
  * synchronises the stream).  Uses library scratch of 64 B per group. */
@@ -251,7 +274,7 @@ int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *p
  *  5. Roe fluxes at the 3 x 17 x 16^2 faces and the default full-step update.
  * HLLE fallbacks of steps 3 and 5 are counted in stat 7.  Arguments, layouts
  * and outputs as in gamer_hydro_solve_batched (padded input); opts may set
- * theta only.  work: device workspace of gamer_ctu_workspace_bytes(n, f32)
+ * theta and bad_count_dev only.  work: device workspace of gamer_ctu_workspace_bytes(n, f32)
  * bytes, 256-byte aligned, owned by the caller; the call launches three
  * kernels and allocates nothing.  Errors as the batched step, plus a missing,
  * short or misaligned workspace and opts fields other than theta. */

@@ -59,6 +59,8 @@ def _lib():
             "gamer_oracle_ctu_solve": (ctypes.c_int, [_PD, _I64, _D, _D, _D, _D, _PD, _PD, _PLL]),
             "gamer_oracle_rtvd_pencil": (ctypes.c_longlong, [_PD, ctypes.c_int, ctypes.c_int, _D, _D, _PD]),
             "gamer_oracle_rtvd_solve": (ctypes.c_int, [_PD, _I64, _D, _D, _D, ctypes.c_int, _PD, _PLL]),
+            "gamer_oracle_margin_reset": (None, [_D]),
+            "gamer_oracle_margin_hits": (ctypes.c_longlong, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -84,6 +86,23 @@ THETA = 1.5  # generalised-minmod parameter of the default reading
 
 def set_threads(n: int) -> None:
     _lib().gamer_oracle_set_threads(int(n))
+
+
+def borderline_decisions(fn, tau):
+    """Run ``fn()`` (a call into the oracle) on one thread and return (its result,
+    the number of fallback decisions it took within a relative margin ``tau`` of
+    their threshold; see gamer_oracle_margin_reset).  Test hook only."""
+    L = _lib()
+    threads = L.gamer_oracle_get_threads()
+    L.gamer_oracle_set_threads(1)
+    L.gamer_oracle_margin_reset(float(tau))
+    try:
+        res = fn()
+        hits = int(L.gamer_oracle_margin_hits())
+    finally:
+        L.gamer_oracle_margin_reset(-1.0)
+        L.gamer_oracle_set_threads(threads)
+    return res, hits
 
 
 def get_threads() -> int:

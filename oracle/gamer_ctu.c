@@ -17,8 +17,10 @@
  *       + dt/(2dh) [F_d(U^{d,-}) - F_d(U^{d,+})]  (direction d alone); if
  *     either state is unphysical both take the cell average (counted);
  *  3. transverse fluxes: Roe fluxes at every face between two E1 cells;
- *  4. correction of the states of direction d of every cell whose
- *     coordinates other than d lie in the interior:
+ *  4. correction of the states the group's faces use: the states of
+ *     direction d of every cell whose coordinates other than d lie in the
+ *     interior, the minus state for c_d = 0..16 and the plus state for
+ *     c_d = -1..15 (the faces 0..16 along d lie between c_d - 1 and c_d):
  *       U^{d,+-} -= dt/(2dh) sum_{d' != d} [Ft_{d'}(c + e_{d'}/2) - Ft_{d'}(c - e_{d'}/2)];
  *     a corrected state that is unphysical keeps its step-2 value (counted
  *     with the predictor fallbacks);
@@ -61,7 +63,9 @@ static int in_e1(int i, int j, int k) {
 /* rho > 0 and p > 0, with p > 0 written as 2 rho E > |m|^2 (p = (gamma-1)
  * (2 rho E - |m|^2) / (2 rho)): the kernels decide with this expression, so a
  * state with p within rounding of zero falls on the same side in both. */
+void gamer_oracle_margin_note_state(const double *U);
 static int physical(const double *U) {
+    gamer_oracle_margin_note_state(U);
     return U[0] > 0.0 && 2.0 * U[0] * U[4] > U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
 }
 static void step(int d, int s, int *i, int *j, int *k) {
@@ -166,6 +170,9 @@ int gamer_oracle_ctu_group(const double *U, double dt, double dh, double g, doub
                                        Ft[(size_t)e * pe + eidx(v, im, jm, km)];
                     }
                     for (int s = 0; s < 2; ++s) {
+                        /* no face of the group uses the minus state of cell -1
+                         * or the plus state of cell 16 along d */
+                        if ((s == 0 && c[d] < 0) || (s == 1 && c[d] >= CI)) continue;
                         double u[CV];
                         double *dst = Ub + (size_t)(2 * d + s) * pe;
                         for (int v = 0; v < CV; ++v) u[v] = dst[eidx(v, i, j, k)] - hdt * corr[v];

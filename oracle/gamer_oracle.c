@@ -76,6 +76,37 @@ void gamer_oracle_set_threads(int n) { oracle_threads = n > 0 ? n : 1; }
 
 int gamer_oracle_get_threads(void) { return oracle_threads; }
 
+/* Test hook, outside the method's arithmetic: a count of the fallback
+ * decisions that sit within a relative margin tau of their threshold, so a
+ * test can bound how many decisions another implementation, rounding
+ * differently, may legitimately take the other way.  A positivity decision on
+ * a state U is counted when |2 rho E - |m|^2| <= tau (|2 rho E| + |m|^2), the
+ * sign of p (the sign of rho is not counted: no state here has rho near 0);
+ * the Roe solver's decision on a2 > 0 when |a2| <= tau (gamma - 1)(|H| +
+ * |u|^2 / 2).  tau < 0 (the default)
+ * turns counting off.  The counter is a plain global: use it with one thread
+ * (gamer_oracle_set_threads(1)). */
+static double margin_tau = -1.0;
+static long long margin_hits = 0;
+
+void gamer_oracle_margin_reset(double tau) {
+    margin_tau = tau;
+    margin_hits = 0;
+}
+
+long long gamer_oracle_margin_hits(void) { return margin_hits; }
+
+void gamer_oracle_margin_note_state(const double *U) {
+    if (margin_tau < 0.0) return;
+    double q = 2.0 * U[0] * U[4], m2 = U[1] * U[1] + U[2] * U[2] + U[3] * U[3];
+    if (fabs(q - m2) <= margin_tau * (fabs(q) + m2)) ++margin_hits;
+}
+
+static void margin_note_a2(double a2, double H, double q2, double g) {
+    if (margin_tau < 0.0) return;
+    if (fabs(a2) <= margin_tau * (g - 1.0) * (fabs(H) + 0.5 * q2)) ++margin_hits;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Ideal-gas state conversions (Toro 2009, Sec. 3.1).                      */
 
@@ -290,6 +321,7 @@ long long gamer_oracle_group_predict(const double *U, const double *W, const dou
                 for (int d = 0; d < 3; ++d)
                     for (int s = 0; s < 2; ++s) {
                         for (int v = 0; v < NV; ++v) pred[d][s][v] = face[d][s][v] + S[v];
+                        gamer_oracle_margin_note_state(pred[d][s]);
                         double w[NV];
                         gamer_oracle_prim_from_cons(pred[d][s], g, w);
                         if (!(w[0] > 0.0) || !(w[4] > 0.0)) bad = 1;
@@ -378,6 +410,7 @@ static double sound_speed(const double *U, double g, double *un) {
 
 static int physical(const double *U, double g) {
     double W[NV];
+    gamer_oracle_margin_note_state(U);
     gamer_oracle_prim_from_cons(U, g, W);
     return W[0] > 0.0 && W[4] > 0.0;
 }
@@ -419,6 +452,7 @@ static int roe_flux_rotated(const double *L, const double *R, double g, double *
     double cL = sound_speed(L, g, &uL);
     double cR = sound_speed(R, g, &uR);
 
+    margin_note_a2(r.a2, r.H, r.u * r.u + r.v * r.v + r.w * r.w, g);
     if (!(r.a2 > 0.0)) {
         hlle(L, R, FL, FR, uL - cL, uR + cR, F);
         return 1;
@@ -641,7 +675,10 @@ int gamer_oracle_hydro_solve_lim(const double *groups_in, int64_t n_groups, doub
 /* stability bound), and the sums are plain dh^3-weighted totals.          */
 
 /* Largest signal-speed sum max_c (|u|+|v|+|w| + 3 c_s), c_s = sqrt(gamma p / rho),
- * over all interior cells of groups [n][5][16][16][16]. */
+ * over all interior cells of groups [n][5][16][16][16].  A cell with rho <= 0,
+ * p <= 0 or a speed that is not finite has no sound speed: the maximum, and so
+ * the time step, is then NaN (undefined) rather than the maximum over the
+ * remaining cells. */
 double gamer_oracle_max_speed(const double *groups, int64_t n_groups, double gamma) {
     const size_t out_sz = (size_t)NV * NI * NI * NI;
     double smax = 0.0;
@@ -653,8 +690,10 @@ double gamer_oracle_max_speed(const double *groups, int64_t n_groups, double gam
                     double u[NV], w[NV];
                     for (int v = 0; v < NV; ++v) u[v] = U[ii(v, i, j, k)];
                     gamer_oracle_prim_from_cons(u, gamma, w);
+                    if (!(w[0] > 0.0) || !(w[4] > 0.0)) return NAN;
                     double cs = sqrt(gamma * w[4] / w[0]);
                     double s = fabs(w[1]) + fabs(w[2]) + fabs(w[3]) + 3.0 * cs;
+                    if (!isfinite(s)) return NAN;
                     if (s > smax) smax = s;
                 }
     }

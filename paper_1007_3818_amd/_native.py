@@ -7,8 +7,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# GAMER_HYDRO_LIB selects another build of the same library (tuning variants)
-LIB_PATH = os.environ.get("GAMER_HYDRO_LIB") or os.path.join(HERE, "libgamer_hydro.so")
+LIB_PATH = os.path.join(HERE, "libgamer_hydro.so")
 
 GAMER_OK = 0
 GAMER_EINVAL = -1
@@ -28,7 +27,8 @@ LIMIT_CHARACTERISTIC = 1
 
 class GamerOpts(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("limiting", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("limiting", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("bad_count_dev", ctypes.c_void_p)]
 
 
 _PO = ctypes.POINTER(GamerOpts)
@@ -43,11 +43,11 @@ SIGNATURES = {
     "gamer_solver_variant_shape": (_I, [_I, _I, _P, _P]),
     "gamer_hydro_solve": (_I, [_P, _I64, _D, _D, _D, _P, _P]),
     "gamer_hydro_solve_f32": (_I, [_P, _I64, _D, _D, _D, _P, _P]),
-    "gamer_hydro_solve_batched": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO]),
-    "gamer_hydro_solve_batched_f32": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO]),
+    "gamer_hydro_solve_batched": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO, _P]),
+    "gamer_hydro_solve_batched_f32": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO, _P]),
     "gamer_hydro_solve_periodic": (_I, [_P, _I, _I, _I, _P, _P, _D, _P, _P, _P, _PO]),
     "gamer_hydro_solve_periodic_f32": (_I, [_P, _I, _I, _I, _P, _P, _D, _P, _P, _P, _PO]),
-    "gamer_hydro_solve_batched_mixed": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO]),
+    "gamer_hydro_solve_batched_mixed": (_I, [_P, _I64, _P, _P, _P, _I, _D, _P, _P, _P, _PO, _P]),
     "gamer_hydro_solve_periodic_mixed": (_I, [_P, _I, _I, _I, _P, _P, _D, _P, _P, _P, _PO]),
     "gamer_step_reduce": (_I, [_P, _I64, _P, _P, _I, _D, _P, _P]),
     "gamer_group_stats": (_I, [_P, _I64, _D, _P]),

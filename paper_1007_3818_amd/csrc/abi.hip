@@ -66,7 +66,8 @@ int scratch(size_t bytes, void **out) {
 
 // Tunables shared by the solver entry points; returns GAMER_OK or an error.
 template <typename T>
-int parse_opts(const gamer_opts *opts, double *theta, int *variant, int64_t *grid, int *limiting) {
+int parse_opts(const gamer_opts *opts, double *theta, int *variant, int64_t *grid, int *limiting,
+               unsigned long long **bad) {
     *theta = (opts && opts->theta != 0.0) ? opts->theta : 1.5;
     if (!(*theta >= 1.0 && *theta <= 2.0)) return fail(GAMER_EINVAL, "theta must lie in [1, 2]");
     *variant = opts ? opts->variant : 0;
@@ -78,6 +79,9 @@ int parse_opts(const gamer_opts *opts, double *theta, int *variant, int64_t *gri
     if (*limiting != GAMER_LIMIT_PRIMITIVE && *limiting != GAMER_LIMIT_CHARACTERISTIC)
         return fail(GAMER_EINVAL, "limiting must be GAMER_LIMIT_PRIMITIVE or GAMER_LIMIT_CHARACTERISTIC");
     if (opts && opts->reserved != 0) return fail(GAMER_EINVAL, "gamer_opts.reserved must be 0");
+    *bad = opts ? reinterpret_cast<unsigned long long *>(opts->bad_count_dev) : nullptr;
+    if (reinterpret_cast<uintptr_t>(*bad) % 8)
+        return fail(GAMER_EINVAL, "gamer_opts.bad_count_dev must be 8-byte aligned");
     return GAMER_OK;
 }
 
@@ -85,14 +89,15 @@ int parse_opts(const gamer_opts *opts, double *theta, int *variant, int64_t *gri
 template <typename S, typename T>
 int solve_common(const S *in, int64_t n, const int8_t *level, const double *dt_dev,
                  const double *dh_dev, int n_levels, double dt, double dh, double gamma,
-                 S *fluxes, S *out, double *stats, const gamer_opts *opts) {
+                 S *fluxes, S *out, double *stats, const gamer_opts *opts, hipStream_t stream) {
     g_err[0] = 0;
     if (n < 0) return fail(GAMER_EINVAL, "n_groups < 0");
     if (!(isfinite(gamma) && gamma > 1.0)) return fail(GAMER_EINVAL, "gamma must be > 1");
     double theta;
     int variant, limiting;
     int64_t grid;
-    if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting)) return e;
+    unsigned long long *bad;
+    if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting, &bad)) return e;
     if (!dt_dev && (!finite_pos(dt) || !finite_pos(dh)))
         return fail(GAMER_EINVAL, "dt and dh must be finite and positive");
     if (n == 0) return GAMER_OK;
@@ -114,8 +119,10 @@ int solve_common(const S *in, int64_t n, const int8_t *level, const double *dt_d
     p.gamma = gamma;
     p.theta = theta;
     p.n_groups = n;
+    p.n_levels = dt_dev ? n_levels : 1;
     p.char_limiting = limiting;
-    return check_hip(launch_solve<S, T>(p, variant, grid, g_stream), "solver launch");
+    p.bad = bad;
+    return check_hip(launch_solve<S, T>(p, variant, grid, stream), "solver launch");
 }
 
 template <typename S, typename T>
@@ -135,7 +142,8 @@ int periodic_common(const S *state, int gx, int gy, int gz, const double *dt_dev
     double theta;
     int variant, limiting;
     int64_t grid;
-    if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting)) return e;
+    unsigned long long *bad;
+    if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting, &bad)) return e;
     SolveParams<S> p;
     p.in = state;
     p.gx = gx;
@@ -151,7 +159,9 @@ int periodic_common(const S *state, int gx, int gy, int gz, const double *dt_dev
     p.gamma = gamma;
     p.theta = theta;
     p.n_groups = n;
+    p.n_levels = 1;
     p.char_limiting = limiting;
+    p.bad = bad;
     return check_hip(launch_solve<S, T>(p, variant, grid, g_stream), "solver launch");
 }
 
@@ -286,9 +296,11 @@ int ctu_common(const T *in, int64_t n, const int8_t *level, const double *dt_dev
     double theta;
     int variant, limiting;
     int64_t grid;
-    if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting)) return e;
+    unsigned long long *bad;
+    if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting, &bad)) return e;
     if (variant != 0 || grid != 0 || limiting != GAMER_LIMIT_PRIMITIVE)
-        return fail(GAMER_EINVAL, "the CTU step takes theta only (variant, grid 0; primitive limiting)");
+        return fail(GAMER_EINVAL,
+                    "the CTU step takes theta and bad_count_dev only (variant, grid 0; primitive limiting)");
     if (n == 0) return GAMER_OK;
     if (!in || !out || !dt_dev || !dh_dev) return fail(GAMER_EINVAL, "NULL array argument");
     if (n_levels < 1 || n_levels > GAMER_MAX_LEVELS)
@@ -297,8 +309,8 @@ int ctu_common(const T *in, int64_t n, const int8_t *level, const double *dt_dev
     if (!work || work_bytes < need) return fail(GAMER_EINVAL, "workspace of %zu bytes required", need);
     if (reinterpret_cast<uintptr_t>(work) % 256) return fail(GAMER_EINVAL, "workspace must be 256-byte aligned");
     if (n * 51 > INT32_MAX) return fail(GAMER_EINVAL, "too many groups for one launch");
-    return check_hip(launch_ctu<T>(in, n, level, dt_dev, dh_dev, gamma, theta, fluxes, out, stats, work,
-                                   g_stream),
+    return check_hip(launch_ctu<T>(in, n, level, n_levels, dt_dev, dh_dev, gamma, theta, fluxes, out, stats,
+                                   bad, work, g_stream),
                      "CTU launch");
 }
 
@@ -321,7 +333,7 @@ int rtvd_common(const T *in, int gx, int gy, int gz, int64_t n, const int8_t *le
         return fail(GAMER_EINVAL, "workspace of %zu bytes required", need);
     if (reinterpret_cast<uintptr_t>(work) % 16) return fail(GAMER_EINVAL, "workspace must be 16-byte aligned");
     if (n * 31 > INT32_MAX) return fail(GAMER_EINVAL, "too many groups for one launch");
-    return check_hip(launch_rtvd<T>(in, gx, gy, gz, n, level, dt_dev, dh_dev, gamma, order,
+    return check_hip(launch_rtvd<T>(in, gx, gy, gz, n, level, n_levels, dt_dev, dh_dev, gamma, order,
                                     static_cast<T *>(work), out, g_stream),
                      "relaxing TVD launch");
 }
@@ -344,7 +356,7 @@ int rtvd_periodic_common(const T *state, int gx, int gy, int gz, const double *d
 
 extern "C" {
 
-int gamer_version(void) { return 100; }
+int gamer_version(void) { return 200; }
 
 int gamer_set_stream(void *hip_stream) {
     g_stream = static_cast<hipStream_t>(hip_stream);
@@ -370,31 +382,38 @@ int gamer_solver_variant_shape(int f32, int variant, int *threads, int *waves_pe
 int gamer_hydro_solve(const double *groups_in, int64_t n_groups, double dt, double dh,
                       double gamma, double *fluxes_out, double *groups_out) {
     return solve_common<double, double>(groups_in, n_groups, nullptr, nullptr, nullptr, 1, dt, dh, gamma,
-                                fluxes_out, groups_out, nullptr, nullptr);
+                                        fluxes_out, groups_out, nullptr, nullptr, g_stream);
 }
 
 int gamer_hydro_solve_f32(const float *groups_in, int64_t n_groups, double dt, double dh,
                           double gamma, float *fluxes_out, float *groups_out) {
     return solve_common<float, float>(groups_in, n_groups, nullptr, nullptr, nullptr, 1, dt, dh, gamma,
-                               fluxes_out, groups_out, nullptr, nullptr);
+                                      fluxes_out, groups_out, nullptr, nullptr, g_stream);
 }
+
+// the stream argument of the batched entry points: NULL keeps the thread's stream
+static hipStream_t pick_stream(void *s) { return s ? static_cast<hipStream_t>(s) : g_stream; }
 
 int gamer_hydro_solve_batched(const double *groups_in, int64_t n_groups, const int8_t *level,
                               const double *dt_dev, const double *dh_dev, int n_levels,
                               double gamma, double *fluxes_out, double *groups_out,
-                              double *group_stats, const gamer_opts *opts) {
+                              double *group_stats, const gamer_opts *opts, void *hip_stream) {
+    g_err[0] = 0;
     if (!dt_dev && n_groups > 0) return fail(GAMER_EINVAL, "NULL dt_dev");
     return solve_common<double, double>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, 0.0,
-                                        0.0, gamma, fluxes_out, groups_out, group_stats, opts);
+                                        0.0, gamma, fluxes_out, groups_out, group_stats, opts,
+                                        pick_stream(hip_stream));
 }
 
 int gamer_hydro_solve_batched_f32(const float *groups_in, int64_t n_groups, const int8_t *level,
                                   const double *dt_dev, const double *dh_dev, int n_levels,
                                   double gamma, float *fluxes_out, float *groups_out,
-                                  double *group_stats, const gamer_opts *opts) {
+                                  double *group_stats, const gamer_opts *opts, void *hip_stream) {
+    g_err[0] = 0;
     if (!dt_dev && n_groups > 0) return fail(GAMER_EINVAL, "NULL dt_dev");
     return solve_common<float, float>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, 0.0, 0.0,
-                               gamma, fluxes_out, groups_out, group_stats, opts);
+                                      gamma, fluxes_out, groups_out, group_stats, opts,
+                                      pick_stream(hip_stream));
 }
 
 int gamer_hydro_solve_periodic(const double *state, int gx, int gy, int gz, const double *dt_dev,
@@ -414,10 +433,12 @@ int gamer_hydro_solve_periodic_f32(const float *state, int gx, int gy, int gz, c
 int gamer_hydro_solve_batched_mixed(const double *groups_in, int64_t n_groups, const int8_t *level,
                                     const double *dt_dev, const double *dh_dev, int n_levels,
                                     double gamma, double *fluxes_out, double *groups_out,
-                                    double *group_stats, const gamer_opts *opts) {
+                                    double *group_stats, const gamer_opts *opts, void *hip_stream) {
+    g_err[0] = 0;
     if (!dt_dev && n_groups > 0) return fail(GAMER_EINVAL, "NULL dt_dev");
     return solve_common<double, float>(groups_in, n_groups, level, dt_dev, dh_dev, n_levels, 0.0, 0.0,
-                                       gamma, fluxes_out, groups_out, group_stats, opts);
+                                       gamma, fluxes_out, groups_out, group_stats, opts,
+                                       pick_stream(hip_stream));
 }
 
 int gamer_hydro_solve_periodic_mixed(const double *state, int gx, int gy, int gz,

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void group_stats_kernel(const T *__restrict__ 
                 u[v] = src[v * NI * NI * NI + k * NI * NI];
                 st[v] += double(u[v]);
             }
-            st[5] = fmax(st[5], double(signal_speed(u[0], u[1], u[2], u[3], u[4], c)));
+            st[5] = max_nan(st[5], double(signal_speed(u[0], u[1], u[2], u[3], u[4], c)));
         }
         // same layout and order as the solver's 320-thread reduction, with
         // the 64 entries of its ghost-cell threads equal to zero
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void group_stats_kernel(const T *__restrict__ 
                 double a = red[q * 320 + t];
                 for (int s = t + 64; s < 320; s += 64) {
                     const double b = red[q * 320 + s];
-                    a = (q == 5) ? fmax(a, b) : a + b;
+                    a = (q == 5) ? max_nan(a, b) : a + b;
                 }
                 acc[q] = a;
             }
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void group_stats_kernel(const T *__restrict__ 
 #pragma unroll
                 for (int q = 0; q < NSTAT; ++q) {
                     const double b = __shfl_down(acc[q], off, 64);
-                    acc[q] = (q == 5) ? fmax(acc[q], b) : acc[q] + b;
+                    acc[q] = (q == 5) ? max_nan(acc[q], b) : acc[q] + b;
                 }
             }
             if (t == 0) {
@@ -120,7 +120,8 @@ __global__ __launch_bounds__(256) void group_stats_kernel(const T *__restrict__ 
 // ---- fixed-order reduction of group stats ----------------------------------
 // One work-group of RT threads.  Thread t folds groups t, t+RT, ... in order;
 // each wave combines its lanes by a fixed shuffle tree and wave 0 combines the
-// waves in order.  The result does not depend on timing.
+// waves in order.  The result does not depend on timing.  Maxima keep NaN, so
+// a level holding a non-physical cell gets a NaN time step.
 constexpr int RT = 1024;
 constexpr int RW = RT / 64;
 
@@ -132,7 +133,7 @@ __device__ void block_fold(double (&x)[N], const bool (&is_max)[N], double (*red
 #pragma unroll
         for (int q = 0; q < N; ++q) {
             const double y = __shfl_down(x[q], off, 64);
-            x[q] = is_max[q] ? fmax(x[q], y) : x[q] + y;
+            x[q] = is_max[q] ? max_nan(x[q], y) : x[q] + y;
         }
     }
     if (lane == 0) {
@@ -144,7 +145,7 @@ __device__ void block_fold(double (&x)[N], const bool (&is_max)[N], double (*red
 #pragma unroll
         for (int q = 0; q < N; ++q) {
             double a = red[q][0];
-            for (int w = 1; w < RW; ++w) a = is_max[q] ? fmax(a, red[q][w]) : a + red[q][w];
+            for (int w = 1; w < RW; ++w) a = is_max[q] ? max_nan(a, red[q][w]) : a + red[q][w];
             x[q] = a;
         }
     }
@@ -164,7 +165,12 @@ __global__ __launch_bounds__(RT) void reduce_kernel(const double *__restrict__ s
         double acc[7] = {0, 0, 0, 0, 0, 0, 0};
         const bool sum7[7] = {false, false, false, false, false, false, false};
         for (int64_t g = t; g < n; g += RT) {
-            const double h = dh_dev ? dh_dev[level ? int(level[g]) : 0] : dh;
+            double h = dh;
+            if (dh_dev) {
+                const int lg = level ? int(level[g]) : 0;
+                // a level out of range is never used as an index; it makes the totals NaN
+                h = (lg >= 0 && lg < n_levels) ? dh_dev[lg] : __builtin_nan("");
+            }
             const double w = h * h * h;
             const double *st = stats + g * NSTAT;
 #pragma unroll
@@ -184,12 +190,13 @@ __global__ __launch_bounds__(RT) void reduce_kernel(const double *__restrict__ s
             double m[1] = {0.0};
             for (int64_t g = t; g < n; g += RT) {
                 const int lg = level ? int(level[g]) : 0;
-                if (lg == L) m[0] = fmax(m[0], stats[g * NSTAT + 5]);
+                if (lg == L) m[0] = max_nan(m[0], stats[g * NSTAT + 5]);
             }
             block_fold(m, max1, red);
             if (t == 0) {
                 const double hL = dh_dev ? dh_dev[L] : dh;
-                dt_out[L] = m[0] > 0.0 ? cfl * hL / m[0] : INFINITY;
+                // NaN when a group of the level has a non-physical cell
+                dt_out[L] = m[0] > 0.0 ? cfl * hL / m[0] : (m[0] != m[0] ? m[0] : INFINITY);
             }
         }
     }

@@ -45,17 +45,18 @@ struct CtuArgs {
     double *stats;        // [n][8] or nullptr
     const int8_t *level;
     const double *dt_dev, *dh_dev;
+    int n_levels;
     double gamma, theta;
     int64_t n_groups;
     T *work;              // [n][WORK_VALUES]
     int *counts;          // [n][2]
+    unsigned long long *bad;  // as in the default solver, or nullptr
 };
 
+// dt and dh of group g (NaN for a level byte out of range, see level_dt)
 template <typename T>
-__device__ __forceinline__ void group_dt(const CtuArgs<T> &P, int64_t g, double &dt, double &dh) {
-    const int lev = P.level ? int(P.level[g]) : 0;
-    dt = P.dt_dev[lev];
-    dh = P.dh_dev[lev];
+__device__ __forceinline__ bool group_dt(const CtuArgs<T> &P, int64_t g, double &dt, double &dh) {
+    return level_dt(P.level, g, P.n_levels, P.dt_dev, P.dh_dev, dt, dh);
 }
 
 template <typename T>
@@ -326,11 +327,13 @@ __global__ __launch_bounds__(256) void ctu_final(CtuArgs<T> P) {
     if (g >= P.n_groups) return;
     const Consts<T> c = make_consts<T>(P.gamma, P.theta);
     double dt, dh;
-    group_dt(P, g, dt, dh);
+    const bool lev_ok = group_dt(P, g, dt, dh);
     const T hdt = T(0.5 * dt / dh);
     const double dtdh = dt / dh;
     const int t = threadIdx.x;
     const int i = t & 15, j = t >> 4;
+    if (!lev_ok && P.bad && t == 0) atomicAdd(P.bad + 1, 1ull);
+    unsigned n_bad = 0;  // output cells that are not physical or not finite
     const T *U = P.in + g * GIN;
     T *out = P.out + g * GOUT;
     int n_pred = 0, n_roe = 0;
@@ -360,7 +363,9 @@ __global__ __launch_bounds__(256) void ctu_final(CtuArgs<T> P) {
                 un[v] = o;
                 st[v] += double(o);
             }
-            st[5] = fmax(st[5], double(signal_speed(un[0], un[1], un[2], un[3], un[4], c)));
+            const double sp = double(signal_speed(un[0], un[1], un[2], un[3], un[4], c));
+            n_bad += sp != sp;
+            st[5] = max_nan(st[5], sp);
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) fz[v] = fzn[v];
@@ -399,6 +404,7 @@ __global__ __launch_bounds__(256) void ctu_final(CtuArgs<T> P) {
     // transverse fluxes, added once by thread 0
     st[6] = double(n_pred) + (t == 0 ? double(P.counts[2 * g]) : 0.0);
     st[7] = double(n_roe) + (t == 0 ? double(P.counts[2 * g + 1]) : 0.0);
+    if (P.bad && n_bad) atomicAdd(P.bad, (unsigned long long)n_bad);
     if (P.stats) block_reduce_stats<256>(st, S.red, P.stats + g * NSTAT);
 }
 
@@ -410,9 +416,9 @@ size_t ctu_workspace_bytes(int64_t n, int elem) {
 }
 
 template <typename T>
-hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double *dt_dev,
+hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, int n_levels, const double *dt_dev,
                       const double *dh_dev, double gamma, double theta, T *fluxes, T *out, double *stats,
-                      void *work, hipStream_t s) {
+                      unsigned long long *bad, void *work, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     CtuArgs<T> P;
     P.in = in;
@@ -422,6 +428,8 @@ hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double 
     P.level = level;
     P.dt_dev = dt_dev;
     P.dh_dev = dh_dev;
+    P.n_levels = n_levels;
+    P.bad = bad;
     P.gamma = gamma;
     P.theta = theta;
     P.n_groups = n;
@@ -435,11 +443,11 @@ hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double 
     return hipGetLastError();
 }
 
-template hipError_t launch_ctu<float>(const float *, int64_t, const int8_t *, const double *,
-                                      const double *, double, double, float *, float *, double *, void *,
-                                      hipStream_t);
-template hipError_t launch_ctu<double>(const double *, int64_t, const int8_t *, const double *,
+template hipError_t launch_ctu<float>(const float *, int64_t, const int8_t *, int, const double *,
+                                      const double *, double, double, float *, float *, double *,
+                                      unsigned long long *, void *, hipStream_t);
+template hipError_t launch_ctu<double>(const double *, int64_t, const int8_t *, int, const double *,
                                        const double *, double, double, double *, double *, double *,
-                                       void *, hipStream_t);
+                                       unsigned long long *, void *, hipStream_t);
 
 }  // namespace gamer

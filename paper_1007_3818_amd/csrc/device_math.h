@@ -49,17 +49,24 @@ __device__ __forceinline__ double sqrt_(double x) {
     return x > 0.0 ? g : (x == 0.0 ? 0.0 : __builtin_nan(""));
 }
 
-// |u| + |v| + |w| + 3 c_s of a conserved state in the working precision.  The
-// solver epilogue and the stand-alone stats kernel both use this function, so
-// their per-group maxima agree bitwise.
+// |u| + |v| + |w| + 3 c_s of a conserved state in the working precision, or NaN
+// when the state is not physical (rho <= 0 or p <= 0) or not finite: such a
+// state has no sound speed, and the NaN carries through the maxima below to
+// the time step instead of being dropped.  The solver epilogue and the
+// stand-alone stats kernel both use this function, so their per-group maxima
+// agree bitwise.
 template <typename T>
 __device__ __forceinline__ T signal_speed(T r, T mx, T my, T mz, T e, const Consts<T> &c) {
     const T ir = rcp(r);
     const T u = mx * ir, v = my * ir, w = mz * ir;
     const T p = c.gm1 * (e - c.half * (mx * u + my * v + mz * w));
     const T cs = sqrt_(c.g * p * ir);
-    return fabs(u) + fabs(v) + fabs(w) + T(3) * cs;
+    const T s = fabs(u) + fabs(v) + fabs(w) + T(3) * cs;
+    return (r > T(0) && p > T(0) && isfinite(s)) ? s : T(__builtin_nan(""));
 }
+
+// Maximum that keeps a NaN of either operand (fmax drops it).
+__device__ __forceinline__ double max_nan(double a, double b) { return (a > b || a != a) ? a : b; }
 
 template <typename T>
 __device__ __forceinline__ Consts<T> make_consts(double gamma, double theta) {

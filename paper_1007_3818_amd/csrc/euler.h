@@ -298,8 +298,8 @@ __device__ __forceinline__ bool roe_dir(const T UL[NV], const T UR[NV], const Co
 }
 
 // Fixed-order reduction of NSTAT doubles per thread over NTHREADS threads:
-// stats 0..4 and 6..7 are summed, stat 5 is a maximum.  Lane 0 of wave 0
-// writes the result.  `red` must hold NTHREADS * NSTAT doubles of LDS.
+// stats 0..4 and 6..7 are summed, stat 5 is a maximum that keeps NaN.  Lane 0
+// of wave 0 writes the result.  `red` must hold NTHREADS * NSTAT doubles of LDS.
 template <int NTHREADS>
 __device__ __forceinline__ void block_reduce_stats(double st[NSTAT], double *red, double *dst) {
     const int t = threadIdx.x;
@@ -313,7 +313,7 @@ __device__ __forceinline__ void block_reduce_stats(double st[NSTAT], double *red
             double a = red[q * NTHREADS + t];
             for (int s = t + 64; s < NTHREADS; s += 64) {
                 const double b = red[q * NTHREADS + s];
-                a = (q == 5) ? fmax(a, b) : a + b;
+                a = (q == 5) ? max_nan(a, b) : a + b;
             }
             acc[q] = a;
         }
@@ -322,7 +322,7 @@ __device__ __forceinline__ void block_reduce_stats(double st[NSTAT], double *red
 #pragma unroll
             for (int q = 0; q < NSTAT; ++q) {
                 const double b = __shfl_down(acc[q], off, 64);
-                acc[q] = (q == 5) ? fmax(acc[q], b) : acc[q] + b;
+                acc[q] = (q == 5) ? max_nan(acc[q], b) : acc[q] + b;
             }
         }
         if (t == 0) {

@@ -38,8 +38,28 @@ struct SolveParams {
     double dt, dh;
     double gamma, theta;
     int64_t n_groups;
+    int n_levels;       // entries of dt_dev and dh_dev
     int char_limiting;  // 0: limit primitive variables, 1: characteristic variables
+    // device counters or nullptr: [0] output cells that are not physical or not
+    // finite, [1] groups whose level byte lies outside [0, n_levels)
+    unsigned long long *bad;
 };
+
+// dt and dh of group g read on the device from its level.  A level byte outside
+// [0, n_levels) is never used as an index: the group gets NaN for both (so its
+// whole output and stats come out NaN) and lev_ok is false.
+__device__ __forceinline__ bool level_dt(const int8_t *level, int64_t g, int n_levels,
+                                         const double *dt_dev, const double *dh_dev, double &dt,
+                                         double &dh) {
+    const int lev = level ? int(level[g]) : 0;
+    if (lev < 0 || lev >= n_levels) {
+        dt = dh = __builtin_nan("");
+        return false;
+    }
+    dt = dt_dev[lev];
+    dh = dh_dev[lev];
+    return true;
+}
 
 // Compiled solver variants (work-group size, occupancy target) and the launcher.
 template <typename T>
@@ -59,7 +79,9 @@ hipError_t launch_group_stats(const T *groups, int64_t n, double gamma, double *
                               hipStream_t s);
 
 // dt_out[L] and totals_out[7] from group stats; dh_dev may be nullptr (then the
-// scalar dh applies to every group, and level must be nullptr too).
+// scalar dh applies to every group, and level must be nullptr too).  A group
+// whose level lies outside [0, n_levels) counts towards no level's dt and
+// makes the totals NaN.
 hipError_t launch_reduce(const double *stats, int64_t n, const int8_t *level, const double *dh_dev,
                          double dh, int n_levels, double cfl, double *dt_out, double *totals_out,
                          hipStream_t s);
@@ -70,16 +92,16 @@ template <typename T>
 size_t rtvd_workspace_elems(int64_t n_groups);
 template <typename T>
 hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int8_t *level,
-                       const double *dt_dev, const double *dh_dev, double gamma, int order, T *work,
-                       T *out, hipStream_t s);
+                       int n_levels, const double *dt_dev, const double *dh_dev, double gamma,
+                       int order, T *work, T *out, hipStream_t s);
 
 // CTU coupling (ctu.hip): workspace bytes for n groups of elem-byte values, and
 // one step of padded groups
 size_t ctu_workspace_bytes(int64_t n, int elem);
 template <typename T>
-hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, const double *dt_dev,
+hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, int n_levels, const double *dt_dev,
                       const double *dh_dev, double gamma, double theta, T *fluxes, T *out, double *stats,
-                      void *work, hipStream_t s);
+                      unsigned long long *bad, void *work, hipStream_t s);
 
 // two refinement levels (amr.hip)
 template <typename T>

@@ -27,6 +27,7 @@ struct SweepArgs {
     T *out;           // [n][5][..] with extent e[d] - 6 along d
     const int8_t *level;
     const double *dt_dev, *dh_dev;
+    int n_levels;     // a level byte outside [0, n_levels) gives the group NaN dt and dh
     double gamma;
     int64_t n_groups;
     int tiles;        // work-groups per group
@@ -94,8 +95,8 @@ __global__ __launch_bounds__(256) void rtvd_sweep_kernel(SweepArgs<T> P) {
     const bool live = q < XPEN && p < ey * ez;
     const int iy = live ? p % ey : 0, iz = live ? p / ey : 0;
 
-    const int lev = P.level ? int(P.level[g]) : 0;
-    const double dt = P.dt_dev[lev], dh = P.dh_dev[lev];
+    double dt, dh;
+    level_dt(P.level, g, P.n_levels, P.dt_dev, P.dh_dev, dt, dh);
     const double dtdx = dt / dh;
     const T g_ = T(P.gamma), gm1 = T(P.gamma - 1.0);
     const T hdt = T(0.5 * dtdx);
@@ -242,8 +243,9 @@ __global__ __launch_bounds__(256) void rtvd_stream_kernel(SweepArgs<T> P) {
     }
     T *dst = P.out + g * NV * vout + int64_t(ia) * so[A] + int64_t(ib) * so[B];
 
-    const int lev = P.level ? int(P.level[g]) : 0;
-    const double dtdx = P.dt_dev[lev] / P.dh_dev[lev];
+    double dt, dh;
+    level_dt(P.level, g, P.n_levels, P.dt_dev, P.dh_dev, dt, dh);
+    const double dtdx = dt / dh;
     const T hdt = T(0.5 * dtdx);
     const T g_ = T(P.gamma), gm1 = T(P.gamma - 1.0);
     constexpr int LSTR[3] = {1, NI, NI * NI};  // strides inside an unpadded group
@@ -304,8 +306,8 @@ size_t rtvd_workspace_elems(int64_t n_groups) {
 
 template <typename T>
 hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int8_t *level,
-                       const double *dt_dev, const double *dh_dev, double gamma, int order, T *work,
-                       T *out, hipStream_t s) {
+                       int n_levels, const double *dt_dev, const double *dh_dev, double gamma,
+                       int order, T *work, T *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int dirs[2][3] = {{0, 1, 2}, {2, 1, 0}};
     T *b1 = work;
@@ -327,6 +329,7 @@ hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int
         P.level = level;
         P.dt_dev = dt_dev;
         P.dh_dev = dh_dev;
+        P.n_levels = n_levels;
         P.gamma = gamma;
         P.n_groups = n;
         const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
@@ -362,10 +365,10 @@ hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int
 
 template size_t rtvd_workspace_elems<float>(int64_t);
 template size_t rtvd_workspace_elems<double>(int64_t);
-template hipError_t launch_rtvd<float>(const float *, int, int, int, int64_t, const int8_t *,
+template hipError_t launch_rtvd<float>(const float *, int, int, int, int64_t, const int8_t *, int,
                                        const double *, const double *, double, int, float *, float *,
                                        hipStream_t);
-template hipError_t launch_rtvd<double>(const double *, int, int, int, int64_t, const int8_t *,
+template hipError_t launch_rtvd<double>(const double *, int, int, int, int64_t, const int8_t *, int,
                                         const double *, const double *, double, int, double *,
                                         double *, hipStream_t);
 

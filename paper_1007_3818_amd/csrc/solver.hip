@@ -37,7 +37,9 @@
 //    or a periodic grid of unpadded groups read in place) and the limited
 //    variables (primitive or characteristic).
 //  - Per-group stats of the updated cells (sums, max signal speed, fallback
-//    counts) are reduced in a fixed order in the epilogue.
+//    counts) are reduced in a fixed order in the epilogue.  An updated cell
+//    that is not physical (rho <= 0, p <= 0) or not finite makes the group's
+//    signal speed NaN and is counted in an optional device counter.
 #include "device_math.h"
 #include "euler.h"
 #include "internal.h"
@@ -135,10 +137,10 @@ void solve_kernel(SolveParams<S_> P) {
     for (int64_t slot = blockIdx.x; slot < P.n_groups; slot += gridDim.x) {
         const int64_t g = xcd_group(slot, P.n_groups);
         double dt = P.dt, dh = P.dh;
-        if (P.dt_dev) {
-            const int lev = P.level ? int(P.level[g]) : 0;
-            dt = P.dt_dev[lev];
-            dh = P.dh_dev[lev];
+        if (P.dt_dev && !level_dt(P.level, g, P.n_levels, P.dt_dev, P.dh_dev, dt, dh)) {
+            // a level byte out of range: the group runs on NaN dt and dh (its
+            // output and stats come out NaN) and is counted once
+            if (P.bad && t == 0) atomicAdd(P.bad + 1, 1ull);
         }
         const double dtdh = dt / dh;
 
@@ -250,6 +252,7 @@ void solve_kernel(SolveParams<S_> P) {
         T fz[NV];            // z flux below the current plane
         double st[6];        // sums of the 5 conserved variables, max signal speed
         int n_pred = 0, n_roe = 0;  // fallback counts
+        unsigned n_bad = 0;  // output cells that are not physical or not finite
 #pragma unroll
         for (int q = 0; q < 6; ++q) st[q] = 0.0;
 #pragma unroll
@@ -498,7 +501,9 @@ void solve_kernel(SolveParams<S_> P) {
                         un[v] = T(o);
                         st[v] += double(o);
                     }
-                    st[5] = fmax(st[5], double(signal_speed(un[0], un[1], un[2], un[3], un[4], c)));
+                    const double sp = double(signal_speed(un[0], un[1], un[2], un[3], un[4], c));
+                    n_bad += sp != sp;
+                    st[5] = max_nan(st[5], sp);
                 }
                 if (!edge) {
 #pragma unroll
@@ -515,6 +520,7 @@ void solve_kernel(SolveParams<S_> P) {
             }
         }
 
+        if (P.bad && n_bad) atomicAdd(P.bad, (unsigned long long)n_bad);
         if (P.stats) {
             double all[NSTAT] = {st[0], st[1], st[2], st[3], st[4], st[5], double(n_pred),
                                  double(n_roe)};

@@ -45,11 +45,36 @@ def _f32(dtype):
     raise TypeError(f"unsupported dtype {dtype}")
 
 
-def _opts(theta, variant, grid, limiting):
-    if theta is None and variant is None and grid is None and limiting is None:
+def _bad_counter(bad_count):
+    """Device address of a bad-cell counter pair: a GPU int64 tensor of two
+    entries (cells not physical or not finite, groups with a level out of range),
+    zeroed by the caller."""
+    if bad_count is None:
+        return None
+    if (not isinstance(bad_count, torch.Tensor) or not bad_count.is_cuda or bad_count.dtype != torch.int64
+            or bad_count.numel() < 2 or not bad_count.is_contiguous()):
+        raise ValueError("bad_count must be a contiguous GPU int64 tensor of at least 2 entries")
+    return bad_count.data_ptr()
+
+
+def _opts(theta, variant, grid, limiting, bad_count=None):
+    if theta is None and variant is None and grid is None and limiting is None and bad_count is None:
         return None
     lim = {None: 0, "primitive": 0, "characteristic": 1}.get(limiting, limiting)
-    return _native.GamerOpts(float(theta or 0.0), int(variant or 0), int(grid or 0), int(lim), 0)
+    return _native.GamerOpts(float(theta or 0.0), int(variant or 0), int(grid or 0), int(lim), 0,
+                             _bad_counter(bad_count))
+
+
+def _levels(level, dt_dev, dh_dev, n):
+    if level is not None:
+        if level.dtype != torch.int8 or not level.is_cuda or level.numel() != n:
+            raise ValueError("level must be a GPU int8 tensor with one entry per group")
+    for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
+        if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 1:
+            raise ValueError(f"{nm} must be a 1-D GPU float64 tensor")
+    if dh_dev.numel() != dt_dev.numel():
+        raise ValueError("dt_dev and dh_dev must have one entry per level")
+    return dt_dev.numel()
 
 
 def _solver_fn(name, dtype, compute):
@@ -81,12 +106,14 @@ def hydro_solve(groups_in, dt, dh, gamma, out=None, fluxes_out=None):
 
 def hydro_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxes_out=None,
                         group_stats=None, theta=None, variant=None, grid=None, limiting=None,
-                        compute=None):
+                        compute=None, bad_count=None):
     """One launch over groups of uneven level; dt and dh read on the device.
     `variant` / `grid` select a compiled solver variant and a persistent grid,
     `limiting` "primitive" or "characteristic" (see gamer_opts); None keeps the
     defaults.  `compute=torch.float32` with float64 arrays selects the FP64-state,
-    FP32-arithmetic path."""
+    FP32-arithmetic path.  `bad_count`: GPU int64 [2] the step adds its counts of
+    non-physical output cells and of groups with a level out of range to.  The
+    launch goes to torch's current stream, passed as the call's stream argument."""
     fn = _solver_fn("gamer_hydro_solve_batched", groups_in.dtype, compute)
     _need(groups_in, (NV, NP, NP, NP), groups_in.dtype, "groups_in")
     n = groups_in.shape[0]
@@ -97,24 +124,18 @@ def hydro_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxe
         _need(fluxes_out, (3, 3, NV, NI, NI), groups_in.dtype, "fluxes_out")
     if group_stats is not None:
         _need(group_stats, (8,), torch.float64, "group_stats")
-    if level is not None:
-        if level.dtype != torch.int8 or not level.is_cuda or level.numel() != n:
-            raise ValueError("level must be a GPU int8 tensor with one entry per group")
-    for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
-        if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 1:
-            raise ValueError(f"{nm} must be a 1-D GPU float64 tensor")
-    n_levels = dt_dev.numel()
-    opts = _opts(theta, variant, grid, limiting)
-    _stream()
+    n_levels = _levels(level, dt_dev, dh_dev, n)
+    opts = _opts(theta, variant, grid, limiting, bad_count)
     _native.check(fn(_ptr(groups_in), n, _ptr(level), _ptr(dt_dev), _ptr(dh_dev), n_levels,
                      float(gamma), _ptr(fluxes_out), _ptr(out), _ptr(group_stats),
-                     ctypes.byref(opts) if opts is not None else None))
+                     ctypes.byref(opts) if opts is not None else None,
+                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
     return out
 
 
 def hydro_solve_periodic(state, gx, gy, gz, dt_dev, dh_dev, gamma, out=None, fluxes_out=None,
                          group_stats=None, theta=None, variant=None, grid=None, limiting=None,
-                         compute=None):
+                         compute=None, bad_count=None):
     """One step of a uniform periodic grid; ghost cells are read from the
     neighbouring groups in place (no padded copy).  `out` must not be `state`.
     Options as in hydro_solve_batched."""
@@ -133,7 +154,7 @@ def hydro_solve_periodic(state, gx, gy, gz, dt_dev, dh_dev, gamma, out=None, flu
     for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
         if t.dtype != torch.float64 or not t.is_cuda or t.numel() < 1:
             raise ValueError(f"{nm} must be a GPU float64 tensor")
-    opts = _opts(theta, variant, grid, limiting)
+    opts = _opts(theta, variant, grid, limiting, bad_count)
     _stream()
     _native.check(fn(_ptr(state), int(gx), int(gy), int(gz), _ptr(dt_dev), _ptr(dh_dev), float(gamma),
                      _ptr(fluxes_out), _ptr(out), _ptr(group_stats),
@@ -223,7 +244,7 @@ def ctu_workspace(n_groups, dtype, device):
 
 
 def ctu_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxes_out=None,
-                      group_stats=None, theta=None, work=None):
+                      group_stats=None, theta=None, work=None, bad_count=None):
     """One step of padded groups with corner-transport-upwind coupling."""
     f32 = _f32(groups_in.dtype)
     _need(groups_in, (NV, NP, NP, NP), groups_in.dtype, "groups_in")
@@ -235,17 +256,12 @@ def ctu_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxes_
         _need(fluxes_out, (3, 3, NV, NI, NI), groups_in.dtype, "fluxes_out")
     if group_stats is not None:
         _need(group_stats, (8,), torch.float64, "group_stats")
-    if level is not None:
-        if level.dtype != torch.int8 or not level.is_cuda or level.numel() != n:
-            raise ValueError("level must be a GPU int8 tensor with one entry per group")
-    for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
-        if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 1:
-            raise ValueError(f"{nm} must be a 1-D GPU float64 tensor")
+    _levels(level, dt_dev, dh_dev, n)
     if work is None:
         work = ctu_workspace(n, groups_in.dtype, groups_in.device)
     if not isinstance(work, torch.Tensor) or not work.is_cuda or not work.is_contiguous():
         raise ValueError("work must be a contiguous GPU tensor")
-    opts = _opts(theta, None, None, None)
+    opts = _opts(theta, None, None, None, bad_count)
     _stream()
     fn = _native.lib().gamer_ctu_solve_batched_f32 if f32 else _native.lib().gamer_ctu_solve_batched
     _native.check(fn(_ptr(groups_in), n, _ptr(level), _ptr(dt_dev), _ptr(dh_dev), dt_dev.numel(),
@@ -282,12 +298,7 @@ def rtvd_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, order=0, out=Non
     if out is None:
         out = torch.empty((n, NV, NI, NI, NI), dtype=groups_in.dtype, device=groups_in.device)
     _need(out, (NV, NI, NI, NI), groups_in.dtype, "out")
-    if level is not None:
-        if level.dtype != torch.int8 or not level.is_cuda or level.numel() != n:
-            raise ValueError("level must be a GPU int8 tensor with one entry per group")
-    for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
-        if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 1:
-            raise ValueError(f"{nm} must be a 1-D GPU float64 tensor")
+    _levels(level, dt_dev, dh_dev, n)
     work = _work(work, n, groups_in.dtype, groups_in.device)
     _stream()
     fn = _native.lib().gamer_rtvd_solve_batched_f32 if f32 else _native.lib().gamer_rtvd_solve_batched

@@ -37,10 +37,29 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_opts_struct_layout():
-    # gamer_opts: double theta, int32 variant, int32 grid, int32 limiting, int32 reserved
-    assert ctypes.sizeof(_native.GamerOpts) == 24
+    # gamer_opts: double theta, int32 variant, int32 grid, int32 limiting, int32 reserved,
+    # uint64_t *bad_count_dev
+    assert ctypes.sizeof(_native.GamerOpts) == 32
     assert _native.GamerOpts.variant.offset == 8 and _native.GamerOpts.grid.offset == 12
     assert _native.GamerOpts.limiting.offset == 16 and _native.GamerOpts.reserved.offset == 20
+    assert _native.GamerOpts.bad_count_dev.offset == 24
+
+
+def test_opts_struct_layout_matches_header(tmp_path):
+    """The C compiler's layout of gamer_opts from the public header."""
+    import subprocess
+    src = tmp_path / "o.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gamer_hydro.h"\n'
+                   'int main(void) { printf("%zu %zu %zu %zu %zu %zu", sizeof(gamer_opts),'
+                   ' offsetof(gamer_opts, variant), offsetof(gamer_opts, grid),'
+                   ' offsetof(gamer_opts, limiting), offsetof(gamer_opts, reserved),'
+                   ' offsetof(gamer_opts, bad_count_dev)); return 0; }\n')
+    exe = tmp_path / "o"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    O = _native.GamerOpts
+    assert got == [ctypes.sizeof(O), O.variant.offset, O.grid.offset, O.limiting.offset, O.reserved.offset,
+                   O.bad_count_dev.offset]
 
 
 def test_solver_variants(lib):
@@ -58,7 +77,7 @@ def test_solver_variants(lib):
 
 
 def test_version(lib):
-    assert lib.gamer_version() >= 100
+    assert lib.gamer_version() >= 200
 
 
 def _rc(fn, *args):
@@ -86,21 +105,24 @@ def test_solve_argument_errors(lib):
 
 def test_batched_argument_errors(lib):
     f = lib.gamer_hydro_solve_batched
-    assert f(P, 4, None, None, P, 1, 1.4, None, P, None, None) == _native.GAMER_EINVAL  # no dt_dev
-    assert f(P, 4, None, P, None, 1, 1.4, None, P, None, None) == _native.GAMER_EINVAL  # no dh_dev
-    assert f(P, 4, None, P, P, 0, 1.4, None, P, None, None) == _native.GAMER_EINVAL
-    assert f(P, 4, None, P, P, 33, 1.4, None, P, None, None) == _native.GAMER_EINVAL
+    assert f(P, 4, None, None, P, 1, 1.4, None, P, None, None, None) == _native.GAMER_EINVAL  # no dt_dev
+    assert f(P, 4, None, P, None, 1, 1.4, None, P, None, None, None) == _native.GAMER_EINVAL  # no dh_dev
+    assert f(P, 4, None, P, P, 0, 1.4, None, P, None, None, None) == _native.GAMER_EINVAL
+    assert f(P, 4, None, P, P, 33, 1.4, None, P, None, None, None) == _native.GAMER_EINVAL
+    bad = _native.GamerOpts(1.5, 0, 0, 0, 0, 0x1004)  # misaligned counter
+    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad), None) == _native.GAMER_EINVAL
+    assert b"bad_count_dev" in lib.gamer_last_error()
     bad = _native.GamerOpts(2.5, 0, 0)
-    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad), None) == _native.GAMER_EINVAL
     bad = _native.GamerOpts(0.5, 0, 0)
-    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad), None) == _native.GAMER_EINVAL
     bad = _native.GamerOpts(1.5, 99, 0)
-    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad), None) == _native.GAMER_EINVAL
     assert b"variant" in lib.gamer_last_error()
     bad = _native.GamerOpts(1.5, -1, 0)
-    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad), None) == _native.GAMER_EINVAL
     bad = _native.GamerOpts(1.5, 0, -4)
-    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad)) == _native.GAMER_EINVAL
+    assert f(P, 4, None, P, P, 1, 1.4, None, P, None, ctypes.byref(bad), None) == _native.GAMER_EINVAL
 
 
 def test_limiting_and_mixed_argument_errors(lib):
@@ -109,16 +131,16 @@ def test_limiting_and_mixed_argument_errors(lib):
     for lim, res in ((2, 0), (-1, 0), (0, 3)):
         bad = _native.GamerOpts(1.5, 0, 0, lim, res)
         assert lib.gamer_hydro_solve_batched(P, 4, None, P, P, 1, 1.4, None, Q, None,
-                                             ctypes.byref(bad)) == E
+                                             ctypes.byref(bad), None) == E
         assert lib.gamer_hydro_solve_periodic_mixed(P, 2, 2, 2, P, P, 1.4, None, Q, None,
                                                     ctypes.byref(bad)) == E
     f = lib.gamer_hydro_solve_batched_mixed
-    assert f(P, 4, None, None, P, 1, 1.4, None, Q, None, None) == E  # no dt_dev
-    assert f(P, 4, None, P, None, 1, 1.4, None, Q, None, None) == E  # no dh_dev
-    assert f(P, 4, None, P, P, 0, 1.4, None, Q, None, None) == E
-    assert f(None, 4, None, P, P, 1, 1.4, None, Q, None, None) == E
+    assert f(P, 4, None, None, P, 1, 1.4, None, Q, None, None, None) == E  # no dt_dev
+    assert f(P, 4, None, P, None, 1, 1.4, None, Q, None, None, None) == E  # no dh_dev
+    assert f(P, 4, None, P, P, 0, 1.4, None, Q, None, None, None) == E
+    assert f(None, 4, None, P, P, 1, 1.4, None, Q, None, None, None) == E
     bad = _native.GamerOpts(1.5, lib.gamer_solver_variants(1), 0, 0, 0)  # float variants index
-    assert f(P, 4, None, P, P, 1, 1.4, None, Q, None, ctypes.byref(bad)) == E
+    assert f(P, 4, None, P, P, 1, 1.4, None, Q, None, ctypes.byref(bad), None) == E
     g = lib.gamer_hydro_solve_periodic_mixed
     assert g(P, 0, 2, 2, P, P, 1.4, None, Q, None, None) == E
     assert g(P, 2, 2, 2, P, P, 1.4, None, P, None, None) == E
@@ -141,7 +163,8 @@ def test_ctu_argument_errors(lib):
         assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, None, W, 1000) == E
         assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, None, ctypes.c_void_p(0x4010), need) == E
         for bad in (_native.GamerOpts(1.5, 1, 0, 0, 0), _native.GamerOpts(1.5, 0, 8, 0, 0),
-                    _native.GamerOpts(1.5, 0, 0, 1, 0), _native.GamerOpts(3.0, 0, 0, 0, 0)):
+                    _native.GamerOpts(1.5, 0, 0, 1, 0), _native.GamerOpts(3.0, 0, 0, 0, 0),
+                    _native.GamerOpts(1.5, 0, 0, 0, 0, 0x1002)):
             assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, ctypes.byref(bad), W, need) == E
         assert f(None, 0, None, None, None, 1, 1.4, None, None, None, None, None, 0) == _native.GAMER_OK
 

@@ -14,22 +14,12 @@ import oracle
 from oracle import amr as oamr
 from oracle_driver import two_level_step
 from paper_1007_3818_amd import amr, hydro, workloads as W
+from parity import state_close
 
 pytestmark = pytest.mark.gpu
 G53 = 5.0 / 3.0
 
 PATCHES = [(1, 1, 1), (2, 1, 1), (1, 2, 1), (1, 1, 2), (3, 2, 1), (0, 3, 3)]
-
-
-def close(gpu, ora, rtol, what=""):
-    gpu = np.asarray(gpu, dtype=np.float64)
-    ora = np.asarray(ora, dtype=np.float64)
-    axes = tuple(i for i in range(ora.ndim) if i != 1)
-    denom = np.abs(ora) + np.abs(ora).max(axis=axes, keepdims=True)
-    err = np.where(denom > 0, np.abs(gpu - ora) / np.where(denom > 0, denom, 1.0),
-                   np.where(gpu == ora, 0.0, np.inf))
-    worst = float(err.max())
-    assert worst <= rtol, f"{what}: max relative error {worst:.3e} > {rtol:.1e}"
 
 
 def layout(gx=2, gy=2, gz=2, coords=PATCHES):
@@ -69,9 +59,9 @@ def test_restrict(gpu, dtype):
     hydro.restrict(fine.to(gpu), torch.from_numpy(parent).to(gpu), c, n_bad=bad)
     got = c.cpu().double().numpy()
     if dtype == torch.float64:
-        close(got, want, 1e-15, "restrict fp64")
+        state_close(got, want, 1e-15, "restrict fp64")
     else:
-        close(got, want, 1e-7, "restrict fp32")  # one float rounding of the double mean
+        state_close(got, want, 1e-7, "restrict fp32")  # one float rounding of the double mean
     cov = amr.covered_mask(2, 2, 2, parent)
     for v in range(5):
         assert np.array_equal(got[:, v][~cov], coarse[:, v].double().numpy()[~cov])
@@ -88,7 +78,7 @@ def test_restrict_skips_and_counts_bad_parents(gpu):
     hydro.restrict(fine, parent, coarse, n_bad=bad)
     assert int(bad.item()) == 1
     want = oamr.restrict(before.cpu().numpy(), fine.cpu().numpy()[2:], [15])
-    close(coarse.cpu().numpy(), want, 1e-15, "one good parent")
+    state_close(coarse.cpu().numpy(), want, 1e-15, "one good parent")
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -105,7 +95,7 @@ def test_flux_correct_random_inputs(gpu, dtype):
     hydro.flux_correct(c, cfl.to(gpu), acc.to(gpu), amr.faces_to_device(faces, gpu), dev1(dt, gpu),
                        dev1(dh, gpu), n_bad=bad)
     assert int(bad.item()) == 0
-    close(c.cpu().numpy(), want, 1e-12 if dtype == torch.float64 else 1e-6, f"flux correct {dtype}")
+    state_close(c.cpu().numpy(), want, 1e-12 if dtype == torch.float64 else 1e-6, f"flux correct {dtype}")
     # cells with no record are untouched
     changed = np.any(want != coarse.double().numpy(), axis=1)
     assert np.array_equal(np.any(c.cpu().double().numpy() != coarse.double().numpy(), axis=1), changed)
@@ -131,7 +121,7 @@ def test_flux_correct_skips_and_counts_bad_records(gpu):
                        dev1(0.02, gpu), n_bad=bad)
     assert int(bad.item()) == 6
     want = oamr.flux_correct(coarse.numpy(), cfl.numpy(), acc.numpy(), faces[6:], 0.01, 0.02)
-    close(c.cpu().numpy(), want, 1e-12, "good records only")
+    state_close(c.cpu().numpy(), want, 1e-12, "good records only")
 
 
 # ---------------------------------------------------------------- the whole step
@@ -220,8 +210,8 @@ def test_two_level_step_against_oracle(gpu, dtype):
     before = hydro.conserved_sums(hydro.restrict(f_gpu, parent_t, c_gpu.clone()), dh)
     got_c, got_f = gpu_two_level_step(c_gpu, f_gpu, parent_t, amr.faces_to_device(faces, gpu), dt, dh, g)
     if dtype == torch.float64:
-        close(got_c.cpu().numpy(), want_c, 1e-12, "two-level coarse")
-        close(got_f.cpu().numpy(), want_f, 1e-12, "two-level fine")
+        state_close(got_c.cpu().numpy(), want_c, 1e-12, "two-level coarse")
+        state_close(got_f.cpu().numpy(), want_f, 1e-12, "two-level fine")
         after = hydro.conserved_sums(got_c, dh)
         scale = np.abs(coarse).sum(axis=(0, 2, 3, 4)) * dh ** 3
         assert np.all(np.abs(np.array(after) - np.array(before)) <= 1e-13 * scale), (before, after)

@@ -1,12 +1,14 @@
 """The corner-transport-upwind (CTU) variant on the GPU, through the C ABI,
 against the oracle's CTU step.
 
-Bars: FP64 within 1e-12 relative to (|oracle| + per-variable max), flux planes
-likewise, fallback counts exact on smooth flow and within 1% on the Mach-10
-flow (positivity decisions on states with p within rounding of zero); FP32 within 1e-5 in L1 per variable (oracle on
-the float-rounded input); a 1D state gives the default path's result in FP64
-to 1e-13 (the transverse fluxes cancel exactly; the two are separate
-compilations); per-level dt and dh read on the device.
+Bars: FP64 within 1e-12 relative per cell (tests/parity.py), flux planes per
+value; fallback counts equal to the oracle's up to the number of the oracle's
+decisions that sit within a relative margin of 1e-9 (about 4.5e6 ulp) of their
+threshold, which a different rounding may take the other way (on these inputs
+there are none, so the counts must be equal); FP32 within 1e-5 in L1 per
+variable (oracle on the float-rounded input); a 1D state gives the default
+path's result in FP64 to 1e-13 (the transverse fluxes cancel exactly; the two
+are separate compilations); per-level dt and dh read on the device.
 """
 import numpy as np
 import pytest
@@ -14,27 +16,10 @@ import torch
 
 import oracle
 from paper_1007_3818_amd import hydro, workloads as W
+from parity import flux_close, l1_rel, state_close
 
 pytestmark = pytest.mark.gpu
 G53 = 5.0 / 3.0
-
-
-def close(gpu, ora, rtol, what=""):
-    gpu = np.asarray(gpu, dtype=np.float64)
-    ora = np.asarray(ora, dtype=np.float64)
-    axes = tuple(i for i in range(ora.ndim) if i != 1)
-    denom = np.abs(ora) + np.abs(ora).max(axis=axes, keepdims=True)
-    err = np.where(denom > 0, np.abs(gpu - ora) / np.where(denom > 0, denom, 1.0),
-                   np.where(gpu == ora, 0.0, np.inf))
-    worst = float(err.max())
-    assert worst <= rtol, f"{what}: max relative error {worst:.3e} > {rtol:.1e}"
-
-
-def l1_rel(gpu, ora):
-    gpu = np.asarray(gpu, dtype=np.float64)
-    den = np.abs(ora).sum(axis=(0, 2, 3, 4))
-    num = np.abs(gpu - ora).sum(axis=(0, 2, 3, 4))
-    return np.where(den > 0, num / np.where(den > 0, den, 1.0), num)
 
 
 def dev1(x, gpu):
@@ -52,27 +37,23 @@ def test_ctu_fp64(gpu, name):
     (st, dh), (gx, gy, gz) = CASES[name][0](), CASES[name][1]
     host = st.numpy()
     dt = oracle.cfl_dt(host, dh, G53, 0.4)
-    ref, ofl, cnt = oracle.hydro_solve(oracle.pack_periodic(host, gx, gy, gz), dt, dh, G53, want_fluxes=True,
-                                       coupling="ctu")
+    pad_h = oracle.pack_periodic(host, gx, gy, gz)
+    (ref, ofl, cnt), borderline = oracle.borderline_decisions(
+        lambda: oracle.hydro_solve(pad_h, dt, dh, G53, want_fluxes=True, coupling="ctu"), 1e-9)
     n = host.shape[0]
     pad = hydro.pack_periodic(st.to(gpu), gx, gy, gz)
     fl = torch.empty((n, 3, 3, 5, 16, 16), dtype=torch.float64, device=gpu)
     stats = torch.empty((n, 8), dtype=torch.float64, device=gpu)
     out = hydro.ctu_solve_batched(pad, None, dev1(dt, gpu), dev1(dh, gpu), G53, fluxes_out=fl,
                                   group_stats=stats)
-    close(out.cpu().numpy(), ref, 1e-12, f"{name} state")
-    close(fl.cpu().numpy().transpose(0, 3, 1, 2, 4, 5), ofl.transpose(0, 3, 1, 2, 4, 5), 1e-12,
-          f"{name} fluxes")
+    state_close(out.cpu().numpy(), ref, 1e-12, f"{name} state")
+    flux_close(fl.cpu().numpy().transpose(0, 3, 1, 2, 4, 5), ofl.transpose(0, 3, 1, 2, 4, 5), 1e-12,
+               f"{name} fluxes")
     s = stats.cpu().numpy()
     got = (int(s[:, 6].sum()), int(s[:, 7].sum()))
-    if name == "smooth48":
-        assert got == cnt
-    else:
-        # Mach-10 flow: a handful of positivity decisions sit on states with p
-        # within rounding of zero, where the kernels' fused multiply-adds and the
-        # oracle's separate roundings may fall on different sides; the states
-        # themselves agree to the 1e-12 bar above
-        assert all(abs(a - b) <= max(2, b // 100) for a, b in zip(got, cnt)), (got, cnt)
+    print(f"[parity] {name}: fallbacks gpu {got} oracle {cnt}, borderline decisions {borderline}")
+    # a decision may differ only where the oracle's own decision is borderline
+    assert abs(got[0] - cnt[0]) + abs(got[1] - cnt[1]) <= borderline, (got, cnt, borderline)
     scale = np.abs(ref).sum(axis=(0, 2, 3, 4))
     assert np.all(np.abs(s[:, :5].sum(axis=0) - ref.sum(axis=(0, 2, 3, 4))) <= 1e-12 * scale)
 
@@ -111,4 +92,4 @@ def test_ctu_levels(gpu):
     out = hydro.ctu_solve_batched(hydro.pack_periodic(st.to(gpu), 2, 2, 2), torch.from_numpy(level).to(gpu),
                                   torch.tensor(dts, dtype=torch.float64, device=gpu),
                                   torch.tensor(dhs, dtype=torch.float64, device=gpu), G53)
-    close(out.cpu().numpy(), ref, 1e-12, "two levels")
+    state_close(out.cpu().numpy(), ref, 1e-12, "two levels")

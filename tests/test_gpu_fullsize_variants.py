@@ -12,29 +12,12 @@ import torch
 
 import oracle
 from paper_1007_3818_amd import hydro, workloads as W
+from parity import l1_rel, state_close
 
 pytestmark = pytest.mark.gpu
 G53 = 5.0 / 3.0
 N = 256
 G = N // 16
-
-
-def close(gpu, ora, rtol, what=""):
-    gpu = np.asarray(gpu, dtype=np.float64)
-    ora = np.asarray(ora, dtype=np.float64)
-    axes = tuple(i for i in range(ora.ndim) if i != 1)
-    denom = np.abs(ora) + np.abs(ora).max(axis=axes, keepdims=True)
-    err = np.where(denom > 0, np.abs(gpu - ora) / np.where(denom > 0, denom, 1.0),
-                   np.where(gpu == ora, 0.0, np.inf))
-    worst = float(err.max())
-    assert worst <= rtol, f"{what}: max relative error {worst:.3e} > {rtol:.1e}"
-
-
-def l1_rel(gpu, ora):
-    gpu = np.asarray(gpu, dtype=np.float64)
-    den = np.abs(ora).sum(axis=(0, 2, 3, 4))
-    num = np.abs(gpu - ora).sum(axis=(0, 2, 3, 4))
-    return np.where(den > 0, num / np.where(den > 0, den, 1.0), num)
 
 
 def sample():
@@ -62,7 +45,7 @@ def test_ctu_full_size_sampled(gpu):
                                       G53, group_stats=stats)
         got = out[idx].cpu().double().numpy()
         if what == "fp64":
-            close(got, ref, 1e-12, "ctu 256^3 fp64")
+            state_close(got, ref, 1e-12, "ctu 256^3 fp64")
         else:
             assert np.all(l1_rel(got, ref) < 1e-5), l1_rel(got, ref)
         assert int(stats[:, 6].sum()) == 0 and int(stats[:, 7].sum()) == 0
@@ -83,7 +66,7 @@ def test_rtvd_full_size_sampled(gpu, order):
         out = hydro.rtvd_solve_periodic(s, G, G, G, dev1(dt, gpu), dev1(dh, gpu), G53, order)
         got = out[idx].cpu().double().numpy()
         if what == "fp64":
-            close(got, ref, 1e-12, f"rtvd 256^3 order {order} fp64")
+            state_close(got, ref, 1e-12, f"rtvd 256^3 order {order} fp64")
         else:
             assert np.all(l1_rel(got, ref) < 1e-5), l1_rel(got, ref)
         del out

@@ -19,27 +19,10 @@ import oracle
 from paper_1007_3818_amd import hydro, workloads as W
 from paper_1007_3818_amd.autotune import max_rel_diff
 from paper_1007_3818_amd.stepper import PeriodicGrid
+from parity import flux_close, l1_rel, state_close
 
 pytestmark = pytest.mark.gpu
 G53 = 5.0 / 3.0
-
-
-def close(gpu, ora, rtol, what=""):
-    gpu = np.asarray(gpu, dtype=np.float64)
-    ora = np.asarray(ora, dtype=np.float64)
-    axes = tuple(i for i in range(ora.ndim) if i != 1)
-    denom = np.abs(ora) + np.abs(ora).max(axis=axes, keepdims=True)
-    err = np.where(denom > 0, np.abs(gpu - ora) / np.where(denom > 0, denom, 1.0),
-                   np.where(gpu == ora, 0.0, np.inf))
-    worst = float(err.max())
-    assert worst <= rtol, f"{what}: max relative error {worst:.3e} > {rtol:.1e}"
-
-
-def l1_rel(gpu, ora):
-    gpu = np.asarray(gpu, dtype=np.float64)
-    den = np.abs(ora).sum(axis=(0, 2, 3, 4))
-    num = np.abs(gpu - ora).sum(axis=(0, 2, 3, 4))
-    return np.where(den > 0, num / np.where(den > 0, den, 1.0), num)
 
 
 # 64 groups of the 4^3-group log-normal state, read as other group grids: every
@@ -101,9 +84,9 @@ def test_fused_fp64_against_oracle(gpu, shape):
     out = hydro.hydro_solve_periodic(st.to(gpu), gx, gy, gz, dt_dev, dh_dev, G53, fluxes_out=fl,
                                      group_stats=stats)
     torch.cuda.synchronize()
-    close(out.cpu().numpy(), ref, 1e-12, f"{shape} state")
-    close(fl.cpu().numpy().transpose(0, 3, 1, 2, 4, 5), ofl.transpose(0, 3, 1, 2, 4, 5), 1e-12,
-          f"{shape} fluxes")
+    state_close(out.cpu().numpy(), ref, 1e-12, f"{shape} state")
+    flux_close(fl.cpu().numpy().transpose(0, 3, 1, 2, 4, 5), ofl.transpose(0, 3, 1, 2, 4, 5), 1e-12,
+               f"{shape} fluxes")
     s = stats.cpu().numpy()
     assert (int(s[:, 6].sum()), int(s[:, 7].sum())) == cnt
 
@@ -137,7 +120,7 @@ def test_fused_full_size_matches_batched(gpu):
     assert torch.equal(a, b)
     pick = sorted(int(x) for x in np.random.default_rng(41).choice(g ** 3, size=64, replace=False))
     ref, _, _ = oracle.hydro_solve(oracle.pack_periodic_subset(host, g, g, g, pick), dt, dh, G53)
-    close(b[torch.as_tensor(pick, device=gpu)].cpu().numpy(), ref, 1e-12, "fused 256^3 fp64")
+    state_close(b[torch.as_tensor(pick, device=gpu)].cpu().numpy(), ref, 1e-12, "fused 256^3 fp64")
 
 
 def test_binding_rejects_aliasing_and_bad_shape(gpu):

@@ -14,27 +14,10 @@ import torch
 
 import oracle
 from paper_1007_3818_amd import hydro, workloads as W
+from parity import l1_rel, state_close
 
 pytestmark = pytest.mark.gpu
 G53 = 5.0 / 3.0
-
-
-def close(gpu, ora, rtol, what=""):
-    gpu = np.asarray(gpu, dtype=np.float64)
-    ora = np.asarray(ora, dtype=np.float64)
-    axes = tuple(i for i in range(ora.ndim) if i != 1)
-    denom = np.abs(ora) + np.abs(ora).max(axis=axes, keepdims=True)
-    err = np.where(denom > 0, np.abs(gpu - ora) / np.where(denom > 0, denom, 1.0),
-                   np.where(gpu == ora, 0.0, np.inf))
-    worst = float(err.max())
-    assert worst <= rtol, f"{what}: max relative error {worst:.3e} > {rtol:.1e}"
-
-
-def l1_rel(gpu, ora):
-    gpu = np.asarray(gpu, dtype=np.float64)
-    den = np.abs(ora).sum(axis=(0, 2, 3, 4))
-    num = np.abs(gpu - ora).sum(axis=(0, 2, 3, 4))
-    return np.where(den > 0, num / np.where(den > 0, den, 1.0), num)
 
 
 def pad3_gpu(state, gx, gy, gz):
@@ -72,7 +55,7 @@ def test_one_step_fp64(gpu, name, order):
     assert bad == 0
     s = st.to(gpu)
     out = hydro.rtvd_solve_batched(pad3_gpu(s, gx, gy, gz), None, dev1(dt, gpu), dev1(dh, gpu), G53, order)
-    close(out.cpu().numpy(), ref, 1e-12, f"{name} order {order}")
+    state_close(out.cpu().numpy(), ref, 1e-12, f"{name} order {order}")
     per = hydro.rtvd_solve_periodic(s, gx, gy, gz, dev1(dt, gpu), dev1(dh, gpu), G53, order)
     assert torch.equal(per, out)
 
@@ -90,7 +73,7 @@ def test_periodic_grid_shapes_fp64(gpu, shape):
         ref, bad = oracle.rtvd_solve(oracle.pack_periodic_rtvd(host, gx, gy, gz), dt, dh, G53, order)
         assert bad == 0
         out = hydro.rtvd_solve_periodic(st.to(gpu), gx, gy, gz, dev1(dt, gpu), dev1(dh, gpu), G53, order)
-        close(out.cpu().numpy(), ref, 1e-12, f"{shape} order {order}")
+        state_close(out.cpu().numpy(), ref, 1e-12, f"{shape} order {order}")
 
 
 @pytest.mark.parametrize("name", ["sod", "smooth48"])
@@ -122,7 +105,7 @@ def test_ten_alternating_steps_fp64(gpu):
         dt = oracle.cfl_dt(host, dh, G53, 0.4)
         host, _ = oracle.rtvd_step_periodic(host, 2, 2, 2, dt, dh, G53, order=k % 2)
         s = hydro.rtvd_solve_periodic(s, 2, 2, 2, dev1(dt, gpu), dev1(dh, gpu), G53, k % 2, work=work)
-    close(s.cpu().numpy(), host, 1e-11, "ten steps")
+    state_close(s.cpu().numpy(), host, 1e-11, "ten steps")
 
 
 def test_levels_read_on_device(gpu):
@@ -139,7 +122,7 @@ def test_levels_read_on_device(gpu):
     out = hydro.rtvd_solve_batched(pad3_gpu(st.to(gpu), 2, 2, 2), torch.from_numpy(level).to(gpu),
                                    torch.tensor(dts, dtype=torch.float64, device=gpu),
                                    torch.tensor(dhs, dtype=torch.float64, device=gpu), G53, 1)
-    close(out.cpu().numpy(), ref, 1e-12, "two levels")
+    state_close(out.cpu().numpy(), ref, 1e-12, "two levels")
 
 
 def test_workspace_checked(gpu):

@@ -19,27 +19,10 @@ import torch
 import oracle
 from paper_1007_3818_amd import hydro, workloads as W
 from paper_1007_3818_amd.autotune import max_rel_diff
+from parity import flux_close, l1_rel, state_close
 
 pytestmark = pytest.mark.gpu
 G53 = 5.0 / 3.0
-
-
-def close(gpu, ora, rtol, what=""):
-    gpu = np.asarray(gpu, dtype=np.float64)
-    ora = np.asarray(ora, dtype=np.float64)
-    axes = tuple(i for i in range(ora.ndim) if i != 1)
-    denom = np.abs(ora) + np.abs(ora).max(axis=axes, keepdims=True)
-    err = np.where(denom > 0, np.abs(gpu - ora) / np.where(denom > 0, denom, 1.0),
-                   np.where(gpu == ora, 0.0, np.inf))
-    worst = float(err.max())
-    assert worst <= rtol, f"{what}: max relative error {worst:.3e} > {rtol:.1e}"
-
-
-def l1_rel(gpu, ora):
-    gpu = np.asarray(gpu, dtype=np.float64)
-    den = np.abs(ora).sum(axis=(0, 2, 3, 4))
-    num = np.abs(gpu - ora).sum(axis=(0, 2, 3, 4))
-    return np.where(den > 0, num / np.where(den > 0, den, 1.0), num)
 
 
 CASES = {
@@ -68,8 +51,8 @@ def test_characteristic_limiting_fp64(gpu, name):
         stats = torch.empty((n, 8), dtype=torch.float64, device=gpu)
         out = hydro.hydro_solve_batched(pad, None, dev1(dt, gpu), dev1(dh, gpu), G53, fluxes_out=fl,
                                         group_stats=stats, variant=v, limiting="characteristic")
-        close(out.cpu().numpy(), ref, 1e-12, f"{name} v{v}")
-        close(fl.cpu().numpy().transpose(0, 3, 1, 2, 4, 5), ofl.transpose(0, 3, 1, 2, 4, 5), 1e-12,
+        state_close(out.cpu().numpy(), ref, 1e-12, f"{name} v{v}")
+        flux_close(fl.cpu().numpy().transpose(0, 3, 1, 2, 4, 5), ofl.transpose(0, 3, 1, 2, 4, 5), 1e-12,
               f"{name} v{v} fluxes")
         s = stats.cpu().numpy()
         assert (int(s[:, 6].sum()), int(s[:, 7].sum())) == cnt
@@ -109,7 +92,7 @@ def test_mixed_precision_one_step(gpu, limiting):
                                              compute=torch.float32)
             assert out.dtype == torch.float64
             if name == "smooth48":
-                close(out.cpu().numpy(), ref, 1e-5, f"mixed {name} v{v}")
+                state_close(out.cpu().numpy(), ref, 1e-5, f"mixed {name} v{v}")
             else:
                 assert np.all(l1_rel(out.cpu().numpy(), ref) < 1e-5), (v, l1_rel(out.cpu().numpy(), ref))
             # on float-representable input the arithmetic is the FP32 path's
