@@ -9,6 +9,15 @@ States are compared per cell:
 c_s = sqrt(gamma p / rho) from the oracle's cell (0 if the oracle's p <= 0).
 A NaN on either side fails the comparison.
 
+Next to a strong contrast (a cell whose neighbours hold 1e4 times its energy)
+the update of a cell sums flux terms far larger than the cell's own value, and
+two correct FP64 evaluations in different rounding orders then differ by far
+more than 1e-12 of that value: the oracle built with fused multiply-adds
+differs from the plain oracle by 1.1e-9 of E on such a cell of the 64^3
+log-normal flow.  For such inputs the tests pass the padded input, and the
+per-cell scale becomes the larger of the cell's own scale and the size of its
+update terms (``update_terms``); both worst errors are printed.
+
 Flux planes are compared per value relative to |oracle| plus the largest
 |oracle| of that flux component over the batch: a face flux has no state of
 its own to scale with, and its error reaches a cell only through the update,
@@ -20,18 +29,58 @@ G53 = 5.0 / 3.0
 NAMES = ("rho", "m_x", "m_y", "m_z", "E")
 
 
-def cell_errors(gpu, ora, gamma=G53):
-    """Per-cell relative errors (same shape as the inputs, (n, 5, ...))."""
-    gpu = np.asarray(gpu, dtype=np.float64)
-    ora = np.asarray(ora, dtype=np.float64)
-    assert gpu.shape == ora.shape and ora.shape[1] == 5, (gpu.shape, ora.shape)
-    rho, E = ora[:, 0], ora[:, 4]
-    m2 = (ora[:, 1:4] ** 2).sum(axis=1)
+def own_scale(U, gamma=G53):
+    """Per-cell scales of a conserved state (n, 5, ...): |rho|, |m| + rho c_s
+    for each momentum component, |E|; also p and c_s (0 where p <= 0)."""
+    U = np.asarray(U, dtype=np.float64)
+    rho, E = U[:, 0], U[:, 4]
+    m2 = (U[:, 1:4] ** 2).sum(axis=1)
     with np.errstate(divide="ignore", invalid="ignore"):
         p = (gamma - 1.0) * (E - 0.5 * m2 / rho)
         cs = np.sqrt(np.where((rho > 0) & (p > 0), gamma * p / rho, 0.0))
     mscale = np.sqrt(m2) + np.abs(rho) * cs
-    scale = np.stack([np.abs(rho), mscale, mscale, mscale, np.abs(E)], axis=1)
+    return np.stack([np.abs(rho), mscale, mscale, mscale, np.abs(E)], axis=1), p, cs
+
+
+def update_terms(padded, dt, dh, gamma=G53):
+    """Per interior cell and variable, the size of the terms its update sums:
+    the cell's own scale plus dt/dh times, over each direction d and the five
+    cells c-2e_d .. c+2e_d its two faces along d depend on, |F_d(U)| + (|u_d| +
+    c_s) times that cell's scale (the upwinding and wave terms of a Riemann flux
+    are such products).  padded: (n, 5, 20, 20, 20)."""
+    pad = np.asarray(padded, dtype=np.float64)
+    sc, p, cs = own_scale(pad, gamma)
+    rho = pad[:, 0]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = pad[:, 1:4] / rho[:, None]
+    p = np.where(np.isfinite(p), p, 0.0)
+    inner = (slice(None), slice(None), slice(2, 18), slice(2, 18), slice(2, 18))
+    out = sc[inner].copy()
+    for d in range(3):
+        ud = u[:, d]
+        F = np.empty_like(pad)
+        F[:, 0] = pad[:, 1 + d]
+        for k in range(3):
+            F[:, 1 + k] = pad[:, 1 + k] * ud + (p if k == d else 0.0)
+        F[:, 4] = (pad[:, 4] + p) * ud
+        T = np.abs(F) + (np.abs(ud) + cs)[:, None] * sc
+        ax = 4 - d  # axes (n, v, z, y, x)
+        for s in range(-2, 3):
+            sl = list(inner)
+            sl[ax] = slice(2 + s, 18 + s)
+            out += (dt / dh) * T[tuple(sl)]
+    return out
+
+
+def cell_errors(gpu, ora, gamma=G53, terms=None):
+    """Per-cell relative errors (same shape as the inputs, (n, 5, ...)).
+    With ``terms`` (from ``update_terms``) the scale is the larger of the two."""
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ora = np.asarray(ora, dtype=np.float64)
+    assert gpu.shape == ora.shape and ora.shape[1] == 5, (gpu.shape, ora.shape)
+    scale = own_scale(ora, gamma)[0]
+    if terms is not None:
+        scale = np.maximum(scale, terms)
     d = np.abs(gpu - ora)
     with np.errstate(divide="ignore", invalid="ignore"):
         return np.where(scale > 0, d / np.where(scale > 0, scale, 1.0), np.where(d == 0, 0.0, np.inf))
@@ -47,10 +96,16 @@ def worst(err):
     return float(err.flat[k]), (int(idx[0]), NAMES[idx[1]], tuple(int(i) for i in idx[2:]))
 
 
-def state_close(gpu, ora, rtol, what="", gamma=G53):
-    """Per-cell comparison of conserved states; prints and returns the worst error."""
-    e, where = worst(cell_errors(gpu, ora, gamma))
-    print(f"[parity] {what}: worst per-cell error {e:.3e} at {where} (bar {rtol:.0e})", flush=True)
+def state_close(gpu, ora, rtol, what="", gamma=G53, terms=None):
+    """Per-cell comparison of conserved states; prints and returns the worst
+    error.  With ``terms`` the bar applies relative to the larger of the cell's
+    own scale and its update terms, and the own-scale worst is printed too."""
+    e, where = worst(cell_errors(gpu, ora, gamma, terms))
+    extra = ""
+    if terms is not None:
+        e0, w0 = worst(cell_errors(gpu, ora, gamma))
+        extra = f"; against the cell's own scale {e0:.3e} at {w0}"
+    print(f"[parity] {what}: worst per-cell error {e:.3e} at {where} (bar {rtol:.0e}){extra}", flush=True)
     assert e <= rtol, f"{what}: per-cell relative error {e:.3e} at {where} > {rtol:.1e}"
     return e
 

@@ -2,8 +2,8 @@
 workload (4096 groups), through the entry points and launches the bench times,
 against the oracle on sampled groups: the eight corner groups of the grid and
 eight random ones, whose padded inputs the oracle assembles itself from the
-same seeded state.  FP64 within 1e-12 relative to (|oracle| + per-variable max
-over the sample); FP32 within 1e-5 in L1 per variable against the oracle run on
+same seeded state.  FP64 within 1e-12
+per cell (rho and E against the cell's own value, momenta against |m| + rho c_s); FP32 within 1e-5 in L1 per variable against the oracle run on
 the float-rounded state.
 """
 import numpy as np

@@ -6,8 +6,10 @@ variant (state, fluxes, per-group stats), for every compiled variant and
 several launch grids: FP64 bitwise; FP32 within 1e-6 relative (the periodic
 kernel is its own instantiation, and the compiler may contract a float
 multiply-add into an FMA in one and not in the other), fallback counts exact.
-Against the oracle's own ghost fill + step: FP64 1e-12 relative (|oracle| +
-per-variable max), FP32 1e-5 in L1 per variable.
+Against the oracle's own ghost fill + step: FP64 1e-12 per cell, relative to
+the larger of the cell's own scale and the size of its update terms (the input
+is a 64^3 log-normal flow with cells beside 1e4 times their own energy), FP32
+1e-5 in L1 per variable.
 Grids are deliberately non-cubic, and include one group wide axes, where a
 group is its own periodic neighbour.
 """
@@ -19,7 +21,7 @@ import oracle
 from paper_1007_3818_amd import hydro, workloads as W
 from paper_1007_3818_amd.autotune import max_rel_diff
 from paper_1007_3818_amd.stepper import PeriodicGrid
-from parity import flux_close, l1_rel, state_close
+from parity import flux_close, l1_rel, state_close, update_terms
 
 pytestmark = pytest.mark.gpu
 G53 = 5.0 / 3.0
@@ -74,8 +76,8 @@ def test_fused_fp64_against_oracle(gpu, shape):
     st = st[: gx * gy * gz].contiguous()
     host = st.numpy()
     dt = oracle.cfl_dt(host, dh, G53, 0.5)
-    ref, ofl, cnt = oracle.hydro_solve(oracle.pack_periodic(host, gx, gy, gz), dt, dh, G53,
-                                       want_fluxes=True)
+    pad = oracle.pack_periodic(host, gx, gy, gz)
+    ref, ofl, cnt = oracle.hydro_solve(pad, dt, dh, G53, want_fluxes=True)
     n = st.shape[0]
     dt_dev = torch.tensor([dt], dtype=torch.float64, device=gpu)
     dh_dev = torch.tensor([dh], dtype=torch.float64, device=gpu)
@@ -84,7 +86,9 @@ def test_fused_fp64_against_oracle(gpu, shape):
     out = hydro.hydro_solve_periodic(st.to(gpu), gx, gy, gz, dt_dev, dh_dev, G53, fluxes_out=fl,
                                      group_stats=stats)
     torch.cuda.synchronize()
-    state_close(out.cpu().numpy(), ref, 1e-12, f"{shape} state")
+    # this 64^3 log-normal flow has cells beside 1e4 times their own energy:
+    # the bar is per cell, relative to the size of the cell's update terms
+    state_close(out.cpu().numpy(), ref, 1e-12, f"{shape} state", terms=update_terms(pad, dt, dh))
     flux_close(fl.cpu().numpy().transpose(0, 3, 1, 2, 4, 5), ofl.transpose(0, 3, 1, 2, 4, 5), 1e-12,
                f"{shape} fluxes")
     s = stats.cpu().numpy()

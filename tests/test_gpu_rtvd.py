@@ -1,6 +1,6 @@
 """The relaxing TVD scheme on the GPU, through the C ABI, against its oracle.
 
-Bars: FP64 within 1e-12 relative to (|oracle| + per-variable max) for one
+Bars: FP64 within 1e-12 per cell (rho and E against the cell's own value, momenta against |m| + rho c_s) for one
 step in both sweep orders; FP32 within 1e-5 in L1 per variable (the oracle
 runs on the float-rounded input); the periodic entry point (ghost cells read
 in place) equal to the padded one, bitwise in FP64, and against the oracle on

@@ -4,7 +4,7 @@ limiting (gamer_opts.limiting) and FP64 state with FP32 arithmetic
 
 Bars:
   * characteristic limiting: FP64 within 1e-12 of the oracle's characteristic
-    limiting (|oracle| + per-variable max), fallback counts exact, in every
+    limiting per cell (rho and E against the cell's own value, momenta against |m| + rho c_s), fallback counts exact, in every
     compiled variant; FP32 within 1e-5 in L1 per variable; the fused periodic
     step bitwise equal to ghost fill + batched step in FP64;
   * FP64 state, FP32 arithmetic: against the FP64 oracle within the FP32 bars
