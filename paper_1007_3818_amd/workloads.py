@@ -95,11 +95,16 @@ def _mode_sum(ks, phases, nx, ny, nz, device, z_lo=0, z_hi=None):
     """sum_m sin(2 pi k_m . x + phi_m) at cell centres of an nx x ny x nz unit-cube grid,
     for z rows z_lo..z_hi.  Evaluated in float64 as Im(prod of 1D complex exponentials)."""
     z_hi = nz if z_hi is None else z_hi
-    two_pi = 2.0 * math.pi
     xs = (torch.arange(nx, dtype=torch.float64, device=device) + 0.5) / nx
     ys = (torch.arange(ny, dtype=torch.float64, device=device) + 0.5) / ny
     zs = (torch.arange(z_lo, z_hi, dtype=torch.float64, device=device) + 0.5) / nz
-    out = torch.zeros((z_hi - z_lo, ny, nx), dtype=torch.float64, device=device)
+    return _mode_sum_at(ks, phases, xs, ys, zs)
+
+
+def _mode_sum_at(ks, phases, xs, ys, zs):
+    """The same sum on the tensor-product grid of the coordinates xs, ys, zs."""
+    two_pi = 2.0 * math.pi
+    out = torch.zeros((len(zs), len(ys), len(xs)), dtype=torch.float64, device=xs.device)
     for (kx, ky, kz), ph in zip(ks.tolist(), phases.tolist()):
         ax = two_pi * kx * xs
         ay = two_pi * ky * ys
@@ -112,16 +117,21 @@ def _mode_sum(ks, phases, nx, ny, nz, device, z_lo=0, z_hi=None):
     return out
 
 
-def smooth_modes(n: int = 256, kmax: int = 4, workload: int = 2, gamma: float = GAMMA,
-                 device="cpu", dtype=torch.float64):
-    """Workloads 2 and 5: smooth periodic flow on an n^3 grid.  Returns (groups, dh)."""
-    assert n % NI == 0
+def _smooth_modes_draws(kmax, workload, gamma):
     r = rng(workload)
     rk, rph = _pick_modes(r, 8, kmax)
     vk = [_pick_modes(r, 8, kmax) for _ in range(3)]
     # each velocity component is a sum of 8 orthogonal unit sines: mean square 4,
     # so |v|^2 averages 12; scale to rms |v| = 0.5 sqrt(gamma)
     vscale = 0.5 * math.sqrt(gamma) / math.sqrt(12.0)
+    return rk, rph, vk, vscale
+
+
+def smooth_modes(n: int = 256, kmax: int = 4, workload: int = 2, gamma: float = GAMMA,
+                 device="cpu", dtype=torch.float64):
+    """Workloads 2 and 5: smooth periodic flow on an n^3 grid.  Returns (groups, dh)."""
+    assert n % NI == 0
+    rk, rph, vk, vscale = _smooth_modes_draws(kmax, workload, gamma)
     g = n // NI
     out = torch.empty((g * g * g, 5, NI, NI, NI), dtype=dtype, device=device)
     # build one z-slab of groups at a time to bound memory at large n
@@ -133,6 +143,27 @@ def smooth_modes(n: int = 256, kmax: int = 4, workload: int = 2, gamma: float = 
         slab = conserved(rho, vel[0], vel[1], vel[2], p, gamma)
         out[gzi * g * g:(gzi + 1) * g * g] = _to_groups(slab, g, g, 1).to(dtype)
     return out, 1.0 / n
+
+
+def smooth_modes_padded(ids, n: int = 1024, kmax: int = 8, workload: int = 5, gamma: float = GAMMA,
+                        ghost: int = 2, device="cpu"):
+    """The listed groups of the same flow with ``ghost`` periodic ghost cells per
+    side, evaluated directly at their cell centres (wrapped into the unit cube),
+    without building the whole grid: (len(ids), 5, 16 + 2 ghost, ...) float64.
+    For inputs of large grids whose sample the CPU must process."""
+    rk, rph, vk, vscale = _smooth_modes_draws(kmax, workload, gamma)
+    g = n // NI
+    m = NI + 2 * ghost
+    out = torch.empty((len(ids), 5, m, m, m), dtype=torch.float64)
+    loc = torch.arange(-ghost, NI + ghost, device=device)
+    for t, gid in enumerate(ids):
+        gid = int(gid)
+        bx, by, bz = gid % g, (gid // g) % g, gid // (g * g)
+        xs, ys, zs = ((((b * NI + loc) % n).to(torch.float64) + 0.5) / n for b in (bx, by, bz))
+        rho = 1.0 + 0.1 * _mode_sum_at(rk, rph, xs, ys, zs)
+        vel = [vscale * _mode_sum_at(k, ph, xs, ys, zs) for k, ph in vk]
+        out[t] = conserved(rho, vel[0], vel[1], vel[2], torch.ones_like(rho), gamma).cpu()
+    return out
 
 
 def _gaussian_field(r: np.random.Generator, n: int, kmin: float, kmax: float, slope: float):
