@@ -236,6 +236,25 @@ int gamer_cfl_dt(const double *groups, int64_t n_groups, double dh, double gamma
 int gamer_cfl_dt_f32(const float *groups, int64_t n_groups, double dh, double gamma, double cfl,
                      double *dt_out, int dt_out_is_device);
 
+/* ---- CFL time step without allocation -----------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * time step as gamer_cfl_dt (same kernels, bitwise the same value) for FP64
+ * interior groups [n][5][16][16][16], written to the device pointer
+ * dt_out_dev, asynchronously on the thread's stream.  The per-group stats go
+ * to a fixed scratch array inside the library, 64 B per group for at most
+ * GAMER_NOALLOC_MAX_GROUPS groups (16 MiB + 256 B per device, held until the
+ * process ends); the call allocates and frees nothing.  The first call on a
+ * device looks up that array's address (hipGetSymbolAddress): make it before
+ * any graph capture.  Calls that overlap on one device (two streams, two
+ * threads) share the array and race.
+ * Errors: GAMER_EINVAL for n_groups < 0 or above GAMER_NOALLOC_MAX_GROUPS,
+ * dh or cfl not finite and positive, gamma <= 1, NULL pointers (n_groups == 0
+ * is a no-op success); GAMER_EHIP for a failed launch. */
+#define GAMER_NOALLOC_MAX_GROUPS 262144
+int gamer_cfl_dt_noalloc(const double *groups, int64_t n_groups, double dh, double gamma, double cfl,
+                         double *dt_out_dev);
+
 /* ---- conserved totals ---------------------------------------------------
  * sums5_out = dh^3 (sum rho, sum m_x, sum m_y, sum m_z, sum E) over interior
  * groups [n][5][16][16][16], accumulated in double in a fixed order.

@@ -14,6 +14,7 @@ GAMER_EINVAL = -1
 GAMER_EHIP = -2
 GAMER_ENOMEM = -3
 MAX_LEVELS = 32
+NOALLOC_MAX_GROUPS = 262144
 
 _P = ctypes.c_void_p
 _D = ctypes.c_double
@@ -54,6 +55,7 @@ SIGNATURES = {
     "gamer_group_stats_f32": (_I, [_P, _I64, _D, _P]),
     "gamer_cfl_dt": (_I, [_P, _I64, _D, _D, _D, _P, _I]),
     "gamer_cfl_dt_f32": (_I, [_P, _I64, _D, _D, _D, _P, _I]),
+    "gamer_cfl_dt_noalloc": (_I, [_P, _I64, _D, _D, _D, _P]),
     "gamer_conserved_sums": (_I, [_P, _I64, _D, _P, _I]),
     "gamer_conserved_sums_f32": (_I, [_P, _I64, _D, _P, _I]),
     "gamer_pack_periodic": (_I, [_P, _I, _I, _I, _P]),

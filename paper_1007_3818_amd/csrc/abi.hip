@@ -11,6 +11,14 @@
 
 using namespace gamer;
 
+// Fixed scratch of gamer_cfl_dt_noalloc: the per-group stats of up to
+// GAMER_NOALLOC_MAX_GROUPS groups, then a 256-byte tail.  Every device the
+// library runs on holds its own copy until the process ends.  In host code this
+// name is not a device address: host code uses only the address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch below).
+constexpr size_t kNoAllocBytes = size_t(GAMER_NOALLOC_MAX_GROUPS) * NSTAT * sizeof(double) + 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -40,7 +48,7 @@ struct Scratch {
 };
 Scratch g_scratch;
 
-int scratch(size_t bytes, void **out) {
+int grow_scratch(size_t bytes, void **out) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
         return fail(GAMER_EHIP, "hipGetDevice failed");
@@ -61,6 +69,30 @@ int scratch(size_t bytes, void **out) {
         g_scratch.size[dev] = want;
     }
     *out = g_scratch.ptr[dev];
+    return GAMER_OK;
+}
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+struct NoAllocScratch {
+    std::mutex mu;
+    void *ptr[64] = {};
+};
+NoAllocScratch g_noalloc;
+
+int noalloc_scratch(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(GAMER_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lock(g_noalloc.mu);
+    if (!g_noalloc.ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(GAMER_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_noalloc.ptr[dev] = p;
+    }
+    *out = g_noalloc.ptr[dev];
     return GAMER_OK;
 }
 
@@ -176,7 +208,7 @@ int cfl_common(const T *groups, int64_t n, double dh, double gamma, double cfl, 
     if (!dt_out) return fail(GAMER_EINVAL, "NULL dt_out");
     if (!groups) return fail(GAMER_EINVAL, "NULL groups");
     void *buf = nullptr;
-    int rc = scratch(size_t(n) * NSTAT * sizeof(double) + 64, &buf);
+    int rc = grow_scratch(size_t(n) * NSTAT * sizeof(double) + 64, &buf);
     if (rc) return rc;
     double *stats = static_cast<double *>(buf);
     double *dt_tmp = stats + size_t(n) * NSTAT;
@@ -204,7 +236,7 @@ int sums_common(const T *groups, int64_t n, double dh, double *sums5, int is_dev
     if (!sums5) return fail(GAMER_EINVAL, "NULL sums5_out");
     if (!groups) return fail(GAMER_EINVAL, "NULL groups");
     void *buf = nullptr;
-    int rc = scratch(size_t(n) * NSTAT * sizeof(double) + 64, &buf);
+    int rc = grow_scratch(size_t(n) * NSTAT * sizeof(double) + 64, &buf);
     if (rc) return rc;
     double *stats = static_cast<double *>(buf);
     double *tot = stats + size_t(n) * NSTAT;  // 7 doubles (56 B) fit in the 64 B tail
@@ -482,6 +514,30 @@ int gamer_cfl_dt(const double *groups, int64_t n_groups, double dh, double gamma
 int gamer_cfl_dt_f32(const float *groups, int64_t n_groups, double dh, double gamma, double cfl,
                      double *dt_out, int dt_out_is_device) {
     return cfl_common<float>(groups, n_groups, dh, gamma, cfl, dt_out, dt_out_is_device);
+}
+
+int gamer_cfl_dt_noalloc(const double *groups, int64_t n_groups, double dh, double gamma, double cfl,
+                         double *dt_out_dev) {
+    g_err[0] = 0;
+    if (n_groups < 0) return fail(GAMER_EINVAL, "n_groups < 0");
+    if (n_groups > GAMER_NOALLOC_MAX_GROUPS)
+        return fail(GAMER_EINVAL, "n_groups %lld above the fixed scratch's %d groups",
+                    (long long)n_groups, GAMER_NOALLOC_MAX_GROUPS);
+    if (!finite_pos(dh) || !finite_pos(cfl) || !(isfinite(gamma) && gamma > 1.0))
+        return fail(GAMER_EINVAL, "dh and cfl must be finite and positive, gamma > 1");
+    if (n_groups == 0) return GAMER_OK;
+    if (!dt_out_dev) return fail(GAMER_EINVAL, "NULL dt_out_dev");
+    if (!groups) return fail(GAMER_EINVAL, "NULL groups");
+    void *buf = nullptr;
+    int rc = noalloc_scratch(&buf);
+    if (rc) return rc;
+    // every group's 8 stats are written before the reduction reads them, so
+    // nothing left by an earlier call is read
+    double *stats = static_cast<double *>(buf);
+    if ((rc = check_hip(launch_group_stats<double>(groups, n_groups, gamma, stats, g_stream), "stats launch")))
+        return rc;
+    return check_hip(launch_reduce(stats, n_groups, nullptr, nullptr, dh, 1, cfl, dt_out_dev, nullptr, g_stream),
+                     "reduce launch");
 }
 
 int gamer_conserved_sums(const double *groups, int64_t n_groups, double dh, double *sums5_out,

@@ -206,6 +206,22 @@ def cfl_dt(groups, dh, gamma, cfl, device_out=False):
     return host.value
 
 
+def cfl_dt_noalloc(groups, dh, gamma, cfl, out=None):
+    """gamer_cfl_dt_noalloc: the CFL time step of FP64 interior groups into a
+    1-element float64 GPU tensor (``out``, or a new one), without any device
+    allocation inside the library (at most NOALLOC_MAX_GROUPS groups)."""
+    _need(groups, (NV, NI, NI, NI), torch.float64, "groups")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=groups.device)
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64
+            and out.is_contiguous() and out.numel() >= 1 and out.device == groups.device):
+        raise ValueError("out must be a contiguous float64 GPU tensor of at least 1 element on the groups' device")
+    _stream()
+    _native.check(_native.lib().gamer_cfl_dt_noalloc(_ptr(groups), groups.shape[0], float(dh), float(gamma),
+                                                     float(cfl), _ptr(out)))
+    return out
+
+
 def conserved_sums(groups, dh, device_out=False):
     f32 = _f32(groups.dtype)
     _need(groups, (NV, NI, NI, NI), groups.dtype, "groups")

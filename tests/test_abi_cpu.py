@@ -29,7 +29,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 37
+    assert len(names) == 38
     for n in names:
         assert hasattr(lib, n), n
         assert n in _native.SIGNATURES, n
@@ -284,6 +284,16 @@ def test_other_entry_point_errors(lib):
     assert lib.gamer_cfl_dt(P, 4, 0.1, 1.4, 0.5, None, 1) == _native.GAMER_EINVAL
     assert lib.gamer_cfl_dt(None, 4, 0.1, 1.4, 0.5, P, 1) == _native.GAMER_EINVAL
     assert lib.gamer_cfl_dt(None, 0, 0.1, 1.4, 0.5, None, 0) == _native.GAMER_OK
+    # the allocation-free variant: every check comes before any device call
+    big = _native.NOALLOC_MAX_GROUPS + 1
+    assert lib.gamer_cfl_dt_noalloc(P, big, 0.1, 1.4, 0.5, P) == _native.GAMER_EINVAL
+    assert b"above the fixed scratch" in lib.gamer_last_error()
+    assert lib.gamer_cfl_dt_noalloc(P, -1, 0.1, 1.4, 0.5, P) == _native.GAMER_EINVAL
+    assert lib.gamer_cfl_dt_noalloc(P, 4, 0.0, 1.4, 0.5, P) == _native.GAMER_EINVAL
+    assert lib.gamer_cfl_dt_noalloc(P, 4, 0.1, 1.0, 0.5, P) == _native.GAMER_EINVAL
+    assert lib.gamer_cfl_dt_noalloc(P, 4, 0.1, 1.4, 0.5, None) == _native.GAMER_EINVAL
+    assert lib.gamer_cfl_dt_noalloc(None, 4, 0.1, 1.4, 0.5, P) == _native.GAMER_EINVAL
+    assert lib.gamer_cfl_dt_noalloc(None, 0, 0.1, 1.4, 0.5, None) == _native.GAMER_OK
     assert lib.gamer_conserved_sums(P, 4, 0.0, P, 1) == _native.GAMER_EINVAL
     assert lib.gamer_conserved_sums(P, 4, 0.1, None, 1) == _native.GAMER_EINVAL
     assert lib.gamer_group_stats(P, 4, 1.0, P) == _native.GAMER_EINVAL
