@@ -193,20 +193,31 @@ void solve_kernel(SolveParams<S_> P) {
         T pre0[NV], pre1[NV];
         auto fetch = [&](int plane) {  // plane in -2..17
             const S_ *src = plane_base(plane + NG);
+            S_ r0[NV], r1[NV];
             if constexpr (!PERIODIC) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    pre0[v] = T(at(src + v * VSTRIDE, unsigned(cp0)));
-                    pre1[v] = T(at(src + v * VSTRIDE, unsigned(cp1)));
+                    r0[v] = at(src + v * VSTRIDE, unsigned(cp0));
+                    r1[v] = at(src + v * VSTRIDE, unsigned(cp1));
                 }
             } else {
                 const S_ *s0 = src + int64_t(gp0) * GOUT + cp0;
                 const S_ *s1 = src + int64_t(gp1) * GOUT + cp1;
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    pre0[v] = T(s0[v * VSTRIDE]);
-                    pre1[v] = T(s1[v * VSTRIDE]);
+                    r0[v] = s0[v * VSTRIDE];
+                    r1[v] = s1[v * VSTRIDE];
                 }
+            }
+            // With double storage and float arithmetic the values are narrowed
+            // here.  Every load is issued before the first conversion, so their
+            // latencies overlap; left to itself the scheduler may pair each load
+            // with its conversion, one memory wait per value.
+            if constexpr (sizeof(S_) != sizeof(T)) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                pre0[v] = T(r0[v]);
+                pre1[v] = T(r1[v]);
             }
         };
         // conserved -> primitive, into the LDS slot of a plane
