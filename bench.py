@@ -452,8 +452,9 @@ def bench_cosmo(tag, steps, warmup, variant, grid):
 
 
 def bench_ctu(tag, state, g, dh, steps, warmup):
-    """The CTU-coupled step (three launches through a workspace) on the padded
-    groups of the same grid, at the MUSCL-Hancock CFL time step."""
+    """The CTU-coupled step on the padded groups of the same grid, at the
+    MUSCL-Hancock CFL time step: the fused z-sweep (one launch, the default) and
+    the pipeline (three launches through a workspace)."""
     import torch
     from paper_1007_3818_amd import hydro
 
@@ -465,25 +466,34 @@ def bench_ctu(tag, state, g, dh, steps, warmup):
     stats = torch.empty((n, 8), dtype=torch.float64, device=dev)
     hydro.group_stats(state, GAMMA, out=stats)
     hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev)
-    work = hydro.ctu_workspace(n, state.dtype, dev)
     out = torch.empty_like(state)
-    for _ in range(warmup):
-        hydro.ctu_solve_batched(padded, None, dt_dev, dh_dev, GAMMA, out=out, group_stats=stats, work=work)
-    torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev[0].record()
-    for _ in range(steps):
-        hydro.ctu_solve_batched(padded, None, dt_dev, dh_dev, GAMMA, out=out, group_stats=stats, work=work)
-    ev[1].record()
-    torch.cuda.synchronize()
-    ms = ev[0].elapsed_time(ev[1]) / steps
-    del work, padded
-    achieved = CTU_FLOPS_PER_CELL * n * CELLS / (ms * 1e-3)
-    return {"ms_per_step": ms, "cell_updates_per_s": n * CELLS / (ms * 1e-3),
-            "roofline": {"bound": "alu", "flops_per_cell": CTU_FLOPS_PER_CELL,
-                         "achieved": achieved / 1e12, "peak": PEAK[tag] / 1e12, "unit": "TFLOP/s",
-                         "frac": achieved / PEAK[tag], "scope": "whole step, three launches"},
-            "step": "CTU coupling, padded input resident, three launches through a workspace"}
+    res = {}
+    for name, variant in (("fused", hydro.CTU_FUSED), ("pipeline", hydro.CTU_PIPELINE)):
+        work = hydro.ctu_workspace(n, state.dtype, dev) if variant == hydro.CTU_PIPELINE else None
+
+        def run():
+            hydro.ctu_solve_batched(padded, None, dt_dev, dh_dev, GAMMA, out=out, group_stats=stats, work=work,
+                                    variant=variant)
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(steps):
+            run()
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / steps
+        del work
+        achieved = CTU_FLOPS_PER_CELL * n * CELLS / (ms * 1e-3)
+        res[name] = {"ms_per_step": ms, "cell_updates_per_s": n * CELLS / (ms * 1e-3),
+                     "roofline": {"bound": "alu", "flops_per_cell": CTU_FLOPS_PER_CELL,
+                                  "achieved": achieved / 1e12, "peak": PEAK[tag] / 1e12, "unit": "TFLOP/s",
+                                  "frac": achieved / PEAK[tag]}}
+    del padded
+    res["step"] = ("CTU coupling, padded input resident: one z-sweeping launch with the intermediates "
+                   "on chip (fused), or three launches through a workspace (pipeline)")
+    return res
 
 
 RTVD_VALUES_PER_GROUP = 16 ** 3 + 2 * (16 * 22 * 22) + 2 * (16 * 16 * 22) + 16 ** 3

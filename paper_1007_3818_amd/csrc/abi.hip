@@ -330,19 +330,23 @@ int ctu_common(const T *in, int64_t n, const int8_t *level, const double *dt_dev
     int64_t grid;
     unsigned long long *bad;
     if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting, &bad)) return e;
-    if (variant != 0 || grid != 0 || limiting != GAMER_LIMIT_PRIMITIVE)
+    if (variant > 1 || grid != 0 || limiting != GAMER_LIMIT_PRIMITIVE)
         return fail(GAMER_EINVAL,
-                    "the CTU step takes theta and bad_count_dev only (variant, grid 0; primitive limiting)");
+                    "the CTU step takes theta, bad_count_dev and variant 0 (fused) or 1 (pipeline) only "
+                    "(grid 0; primitive limiting)");
     if (n == 0) return GAMER_OK;
     if (!in || !out || !dt_dev || !dh_dev) return fail(GAMER_EINVAL, "NULL array argument");
     if (n_levels < 1 || n_levels > GAMER_MAX_LEVELS)
         return fail(GAMER_EINVAL, "n_levels must lie in [1, %d]", GAMER_MAX_LEVELS);
-    const size_t need = ctu_workspace_bytes(n, int(sizeof(T)));
-    if (!work || work_bytes < need) return fail(GAMER_EINVAL, "workspace of %zu bytes required", need);
-    if (reinterpret_cast<uintptr_t>(work) % 256) return fail(GAMER_EINVAL, "workspace must be 256-byte aligned");
-    if (n * 51 > INT32_MAX) return fail(GAMER_EINVAL, "too many groups for one launch");
+    if (n > INT32_MAX / 51) return fail(GAMER_EINVAL, "too many groups for one launch");
+    if (variant == 1) {
+        const size_t need = ctu_workspace_bytes(n, int(sizeof(T)));
+        if (!work || work_bytes < need) return fail(GAMER_EINVAL, "workspace of %zu bytes required", need);
+        if (reinterpret_cast<uintptr_t>(work) % 256)
+            return fail(GAMER_EINVAL, "workspace must be 256-byte aligned");
+    }
     return check_hip(launch_ctu<T>(in, n, level, n_levels, dt_dev, dh_dev, gamma, theta, fluxes, out, stats,
-                                   bad, work, g_stream),
+                                   bad, variant, work, g_stream),
                      "CTU launch");
 }
 

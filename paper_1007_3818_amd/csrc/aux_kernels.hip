@@ -124,6 +124,7 @@ __global__ __launch_bounds__(256) void group_stats_kernel(const T *__restrict__ 
 // a level holding a non-physical cell gets a NaN time step.
 constexpr int RT = 1024;
 constexpr int RW = RT / 64;
+constexpr int RU = 4;  // groups per thread whose loads are in flight together
 
 template <int N>
 __device__ void block_fold(double (&x)[N], const bool (&is_max)[N], double (*red)[RW]) {
@@ -164,19 +165,38 @@ __global__ __launch_bounds__(RT) void reduce_kernel(const double *__restrict__ s
         // stats 0..4 weighted by dh^3 of the group's level, then stats 6 and 7
         double acc[7] = {0, 0, 0, 0, 0, 0, 0};
         const bool sum7[7] = {false, false, false, false, false, false, false};
-        for (int64_t g = t; g < n; g += RT) {
-            double h = dh;
-            if (dh_dev) {
-                const int lg = level ? int(level[g]) : 0;
-                // a level out of range is never used as an index; it makes the totals NaN
-                h = (lg >= 0 && lg < n_levels) ? dh_dev[lg] : __builtin_nan("");
-            }
-            const double w = h * h * h;
-            const double *st = stats + g * NSTAT;
+        // RU groups' loads are issued before any is folded (a single pass over
+        // 10^5 groups is otherwise one memory latency per group per thread); the
+        // fold order stays t, t + RT, t + 2 RT, ...
+        for (int64_t g0 = t; g0 < n; g0 += int64_t(RT) * RU) {
+            double s[RU][7], w[RU];
+            bool ok[RU];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) acc[q] += w * st[q];
-            acc[5] += st[6];
-            acc[6] += st[7];
+            for (int u = 0; u < RU; ++u) {
+                const int64_t g1 = g0 + int64_t(u) * RT;
+                ok[u] = g1 < n;
+                const int64_t g = ok[u] ? g1 : g0;  // a valid group to read; its values are not used
+                double h = dh;
+                if (dh_dev) {
+                    const int lg = level ? int(level[g]) : 0;
+                    // a level out of range is never used as an index; it makes the totals NaN
+                    h = (lg >= 0 && lg < n_levels) ? dh_dev[lg] : __builtin_nan("");
+                }
+                w[u] = h * h * h;
+                const double *st = stats + g * NSTAT;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) s[u][q] = st[q];
+                s[u][5] = st[6];
+                s[u][6] = st[7];
+            }
+#pragma unroll
+            for (int u = 0; u < RU; ++u) {
+                if (!ok[u]) continue;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) acc[q] += w[u] * s[u][q];
+                acc[5] += s[u][5];
+                acc[6] += s[u][6];
+            }
         }
         block_fold(acc, sum7, red);
         if (t == 0) {
@@ -188,9 +208,19 @@ __global__ __launch_bounds__(RT) void reduce_kernel(const double *__restrict__ s
         const bool max1[1] = {true};
         for (int L = 0; L < n_levels; ++L) {
             double m[1] = {0.0};
-            for (int64_t g = t; g < n; g += RT) {
-                const int lg = level ? int(level[g]) : 0;
-                if (lg == L) m[0] = max_nan(m[0], stats[g * NSTAT + 5]);
+            for (int64_t g0 = t; g0 < n; g0 += int64_t(RT) * RU) {
+                double sp[RU];
+                bool take[RU];
+#pragma unroll
+                for (int u = 0; u < RU; ++u) {
+                    const int64_t g1 = g0 + int64_t(u) * RT;
+                    const int64_t g = g1 < n ? g1 : g0;
+                    take[u] = g1 < n && (level ? int(level[g]) : 0) == L;
+                    sp[u] = stats[g * NSTAT + 5];
+                }
+#pragma unroll
+                for (int u = 0; u < RU; ++u)
+                    if (take[u]) m[0] = max_nan(m[0], sp[u]);
             }
             block_fold(m, max1, red);
             if (t == 0) {

@@ -1,9 +1,25 @@
 // ctu.hip -- the corner-transport-upwind (CTU) coupling of the MUSCL-Hancock
 // step: face states predicted along their own direction, corrected by upwind
 // transverse Roe fluxes, then the final Roe fluxes and the same full-step
-// update as the default path.  Unlike the fused z-sweep solver this variant
-// keeps its intermediate arrays in a caller-provided workspace and runs as a
-// short pipeline of launches, one stage each:
+// update as the default path.  Two implementations:
+//
+// ctu_fused (variant 0, the default): one work-group per group sweeping z with
+// every intermediate on chip.  Thread t < 324 owns the column (i, j) of the
+// 18 x 18 square of cells -1..16; step s (planes s = -1..16):
+//   A  the z predictor of plane s, the transverse z flux between planes s - 1
+//      and s (registers: this thread holds the plus-z state below), the
+//      corrections of plane s - 1's x and y states (they need that flux and the
+//      one below it, both in registers, and plane s - 1's transverse x and y
+//      fluxes from LDS), then the x and y predictor of plane s;
+//   C  (after a barrier) the transverse x and y fluxes of plane s and the final
+//      x and y fluxes of plane s - 1, into LDS;
+//   E  (after a barrier) the corrected z states of plane s, the final z flux
+//      between planes s - 1 and s, the update of plane s - 1 and the primitive
+//      states of padded plane s + 2 into the ring.
+// Nothing is written to memory but the result, the flux planes and the stats.
+//
+// The pipeline (variant 1) keeps its intermediate arrays in a caller-provided
+// workspace and runs as a short sequence of launches, one stage each:
 //   ctu_zero      clear the per-group fallback counters
 //   ctu_predict   one work-group per group sweeping z: slopes and the
 //                 one-direction Hancock predictor on the cells of [-1,16]^3
@@ -408,6 +424,316 @@ __global__ __launch_bounds__(256) void ctu_final(CtuArgs<T> P) {
     if (P.stats) block_reduce_stats<256>(st, S.red, P.stats + g * NSTAT);
 }
 
+
+// ---- the fused z-sweep (variant 0) -------------------------------------------
+
+template <typename T>
+struct FusedLds {
+    union {
+        struct {
+            T w[3][NV][NP][NP];    // primitive states of padded planes: plane m in slot (m + 3) % 3
+            T xm[NV][CE][CE];      // predicted minus-x state of plane s at [v][j + 1][i + 1]
+            T ym[NV][CE][CE];      // predicted minus-y state, likewise
+            T ftx[NV][CE][CE];     // transverse x flux of plane s at face (i + 1/2, j): [v][j + 1][i + 1]
+            T fty[NV][CE][CE];     // transverse y flux at face (i, j + 1/2): [v][j + 1][i + 1]
+            T cxp[NV][NI][NI + 1];  // corrected plus-x state of plane s - 1, cell (f - 1, j) at [v][j][f]
+            T cyp[NV][NI + 1][NI];  // corrected plus-y state, cell (i, f - 1) at [v][f][i]
+            T fx[NV][NI][NI + 1];   // final x flux of plane s - 1 at face f of row j: [v][j][f]
+            T fy[NV][NI + 1][NI];   // final y flux at face f of column i: [v][f][i]
+        } a;
+        double red[384 * NSTAT];  // the stats reduction, after the sweep
+    };
+};
+
+// Work-group size: one thread per cell of an 18 x 18 plane (324 of 384 busy).
+// LDS: 70 KB in float (two work-groups per CU, three waves per SIMD), 140 KB in
+// double (one work-group per CU).
+constexpr int FUSED_THREADS = 384;
+
+template <typename T>
+struct FusedWaves;
+template <>
+struct FusedWaves<float> {
+    static constexpr int waves = 3;
+};
+template <>
+struct FusedWaves<double> {
+    static constexpr int waves = 2;
+};
+
+// u = p - hdt (a + b), or p itself (and false) when that leaves the physical
+// set; a, b are the two transverse flux differences in the order of the
+// pipeline's `corrected` (the lower direction first)
+template <typename T>
+__device__ __forceinline__ bool correct_state(const T p[NV], const T a[NV], const T b[NV], T hdt, T u[NV]) {
+    T q[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const T corr = a[v] + b[v];
+        q[v] = p[v] - hdt * corr;
+    }
+    if (!physical(q)) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = p[v];
+        return false;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = q[v];
+    return true;
+}
+
+template <typename T>
+__global__ __attribute__((amdgpu_flat_work_group_size(FUSED_THREADS, FUSED_THREADS),
+                          amdgpu_waves_per_eu(FusedWaves<T>::waves, 8)))
+void ctu_fused(CtuArgs<T> P) {
+    constexpr int NT = FUSED_THREADS;
+    static_assert(NT >= CE * CE, "one thread per cell of a plane");
+    __shared__ FusedLds<T> S;
+    const int64_t g = blockIdx.x;
+    if (g >= P.n_groups) return;
+    const Consts<T> c = make_consts<T>(P.gamma, P.theta);
+    double dt, dh;
+    const bool lev_ok = group_dt(P, g, dt, dh);
+    const T hdt = T(0.5 * dt / dh);
+    const double dtdh = dt / dh;
+    const T *U = P.in + g * GIN;
+    T *out = P.out + g * GOUT;
+    const int t = threadIdx.x;
+    if (!lev_ok && P.bad && t == 0) atomicAdd(P.bad + 1, 1ull);
+    const bool mine = t < CE * CE;
+    const int i = t % CE - 1, j = t / CE - 1;  // this thread's column, meaningful when mine
+    const int ii = i + NG, jj = j + NG;        // its padded position
+    const bool in_i = i >= 0 && i < NI, in_j = j >= 0 && j < NI;
+    int n_pred = 0, n_roe = 0;
+    unsigned n_bad = 0;
+    double st[NSTAT];
+#pragma unroll
+    for (int q = 0; q < NSTAT; ++q) st[q] = 0.0;
+
+    // carried from step s - 1 to step s
+    T zpp[NV];   // predicted plus-z state of plane s - 1 (transverse z flux)
+    T czp[NV];   // corrected plus-z state of plane s - 1 (final z flux)
+    T ftzb[NV];  // transverse z flux below plane s - 1
+    T fzb[NV];   // final z flux below plane s - 1
+    T xp[NV], yp[NV];  // predicted plus-x and plus-y states of plane s - 1
+#pragma unroll
+    for (int v = 0; v < NV; ++v) zpp[v] = czp[v] = ftzb[v] = fzb[v] = xp[v] = yp[v] = T(0);
+
+    auto fill = [&](int m) {  // padded plane m (-2..17) into its ring slot
+        const int slot = (m + 3) % 3;
+        for (int q = t; q < NPL; q += NT) {
+            const int qi = q % NP, qj = q / NP;
+            T w[NV];
+            prim_at(U, qi - NG, qj - NG, m, c, w);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) S.a.w[slot][v][qj][qi] = w[v];
+        }
+    };
+    // cell average of padded cell (i, j, k): the predictor's first-order fallback
+    auto average = [&](int k, T u[NV]) {
+        const int o = ((k + NG) * NP + jj) * NP + ii;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) u[v] = U[o + v * NP * NP * NP];
+    };
+    fill(-2);
+    fill(-1);
+    fill(0);
+
+    for (int s = -1; s <= NI; ++s) {
+        __syncthreads();  // B0: padded planes s - 1, s, s + 1 in the ring
+        const int sm = (s + 2) % 3, s0 = (s + 3) % 3, sp = (s + 4) % 3;
+        const bool e1 = mine && in_e1(i, j, s);
+        const int kb = s - 1;  // the plane whose x / y states are corrected and fluxes finished
+
+        // ---- A: z predictor, transverse z flux, corrections of plane s - 1, x / y predictor
+        T W0[NV], zm[NV], zpn[NV], ftz[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) W0[v] = zm[v] = zpn[v] = ftz[v] = T(0);
+        if (e1) {
+            T wl[NV], wr[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                W0[v] = S.a.w[s0][v][jj][ii];
+                wl[v] = S.a.w[sm][v][jj][ii];
+                wr[v] = S.a.w[sp][v][jj][ii];
+            }
+            if (!predict_from<2>(W0, wl, wr, hdt, c, zm, zpn)) {
+                ++n_pred;
+                average(s, zm);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) zpn[v] = zm[v];
+            }
+            if (s >= 0 && in_e1(i, j, s - 1)) n_roe += roe_dir<2>(zpp, zm, c, ftz);
+        }
+        // corrected x and y states of plane kb (whose other two coordinates lie in
+        // the interior); the plus states go to LDS for the neighbour's face
+        T cxm[NV], cym[NV];
+        if (mine && kb >= 0 && kb < NI) {
+            T a[NV], b[NV], u[NV], p[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) b[v] = ftz[v] - ftzb[v];
+            if (in_j) {  // x states: y and z differences
+#pragma unroll
+                for (int v = 0; v < NV; ++v) a[v] = S.a.fty[v][j + 1][i + 1] - S.a.fty[v][j][i + 1];
+                if (i >= 0) {  // minus-x state: face i
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) p[v] = S.a.xm[v][j + 1][i + 1];
+                    n_pred += !correct_state(p, a, b, hdt, cxm);
+                }
+                if (i < NI) {  // plus-x state: face i + 1
+                    n_pred += !correct_state(xp, a, b, hdt, u);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) S.a.cxp[v][j][i + 1] = u[v];
+                }
+            }
+            if (in_i) {  // y states: x and z differences
+#pragma unroll
+                for (int v = 0; v < NV; ++v) a[v] = S.a.ftx[v][j + 1][i + 1] - S.a.ftx[v][j + 1][i];
+                if (j >= 0) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) p[v] = S.a.ym[v][j + 1][i + 1];
+                    n_pred += !correct_state(p, a, b, hdt, cym);
+                }
+                if (j < NI) {
+                    n_pred += !correct_state(yp, a, b, hdt, u);
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) S.a.cyp[v][j + 1][i] = u[v];
+                }
+            }
+        }
+        if (e1) {
+            T wl[NV], wr[NV], um[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                wl[v] = S.a.w[s0][v][jj][ii - 1];
+                wr[v] = S.a.w[s0][v][jj][ii + 1];
+            }
+            if (!predict_from<0>(W0, wl, wr, hdt, c, um, xp)) {
+                ++n_pred;
+                average(s, um);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) xp[v] = um[v];
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                S.a.xm[v][j + 1][i + 1] = um[v];
+                wl[v] = S.a.w[s0][v][jj - 1][ii];
+                wr[v] = S.a.w[s0][v][jj + 1][ii];
+            }
+            if (!predict_from<1>(W0, wl, wr, hdt, c, um, yp)) {
+                ++n_pred;
+                average(s, um);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) yp[v] = um[v];
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) S.a.ym[v][j + 1][i + 1] = um[v];
+        }
+        __syncthreads();  // B1: minus states of plane s and corrected plus states of plane kb
+
+        // ---- C: transverse x / y fluxes of plane s, final x / y fluxes of plane kb
+        if (e1) {
+            T R[NV], F[NV];
+            if (in_e1(i + 1, j, s)) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) R[v] = S.a.xm[v][j + 1][i + 2];
+                n_roe += roe_dir<0>(xp, R, c, F);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) S.a.ftx[v][j + 1][i + 1] = F[v];
+            }
+            if (in_e1(i, j + 1, s)) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) R[v] = S.a.ym[v][j + 2][i + 1];
+                n_roe += roe_dir<1>(yp, R, c, F);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) S.a.fty[v][j + 1][i + 1] = F[v];
+            }
+        }
+        if (mine && kb >= 0 && kb < NI) {
+            T L[NV], F[NV];
+            if (in_j && i >= 0) {  // x face i of row j: plus-x of cell i - 1, minus-x of cell i
+#pragma unroll
+                for (int v = 0; v < NV; ++v) L[v] = S.a.cxp[v][j][i];
+                n_roe += roe_dir<0>(L, cxm, c, F);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) S.a.fx[v][j][i] = F[v];
+                if (P.flux && (i & 7) == 0) {
+                    T *dst = P.flux + g * GFLX + ((0 * 3 + (i >> 3)) * NV) * NINNER + kb * NI + j;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = F[v];
+                }
+            }
+            if (in_i && j >= 0) {  // y face j of column i
+#pragma unroll
+                for (int v = 0; v < NV; ++v) L[v] = S.a.cyp[v][j][i];
+                n_roe += roe_dir<1>(L, cym, c, F);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) S.a.fy[v][j][i] = F[v];
+                if (P.flux && (j & 7) == 0) {
+                    T *dst = P.flux + g * GFLX + ((1 * 3 + (j >> 3)) * NV) * NINNER + kb * NI + i;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = F[v];
+                }
+            }
+        }
+        __syncthreads();  // B2: transverse fluxes of plane s, final x / y fluxes of plane kb
+
+        // ---- E: corrected z states of plane s, final z flux below it, update of plane kb
+        if (mine && in_i && in_j) {
+            T a[NV], b[NV], czm[NV], fz[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                fz[v] = T(0);
+                a[v] = S.a.ftx[v][j + 1][i + 1] - S.a.ftx[v][j + 1][i];
+                b[v] = S.a.fty[v][j + 1][i + 1] - S.a.fty[v][j][i + 1];
+            }
+            if (s >= 0) n_pred += !correct_state(zm, a, b, hdt, czm);
+            if (s >= 0) {  // final z flux at face s: plus-z of plane s - 1, minus-z of plane s
+                n_roe += roe_dir<2>(czp, czm, c, fz);
+                if (P.flux && (s & 7) == 0) {
+                    T *dst = P.flux + g * GFLX + ((2 * 3 + (s >> 3)) * NV) * NINNER + j * NI + i;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = fz[v];
+                }
+            }
+            if (kb >= 0) {
+                // plane kb is complete: U - dt/dh ((dF_x + dF_y) + dF_z)
+                T un[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double dxy = (double(S.a.fx[v][j][i + 1]) - double(S.a.fx[v][j][i])) +
+                                       (double(S.a.fy[v][j + 1][i]) - double(S.a.fy[v][j][i]));
+                    const double dfz = double(fz[v]) - double(fzb[v]);
+                    const double u0 = double(U[v * (NP * NP * NP) + ((kb + NG) * NP + jj) * NP + ii]);
+                    const T o = T(u0 - dtdh * (dxy + dfz));
+                    out[v * (NI * NI * NI) + (kb * NI + j) * NI + i] = o;
+                    un[v] = o;
+                    st[v] += double(o);
+                }
+                const double sp_ = double(signal_speed(un[0], un[1], un[2], un[3], un[4], c));
+                n_bad += sp_ != sp_;
+                st[5] = max_nan(st[5], sp_);
+            }
+            if (s < NI) n_pred += !correct_state(zpn, a, b, hdt, czp);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fzb[v] = fz[v];
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            zpp[v] = zpn[v];
+            ftzb[v] = ftz[v];
+        }
+        if (s + 2 <= NI + 1) fill(s + 2);  // into the slot of plane s - 1, no longer read
+    }
+    if (P.bad && n_bad) atomicAdd(P.bad, (unsigned long long)n_bad);
+    if (P.stats) {
+        st[6] = double(n_pred);
+        st[7] = double(n_roe);
+        __syncthreads();  // the ring and the plane arrays are no longer read
+        block_reduce_stats<NT>(st, S.red, P.stats + g * NSTAT);
+    }
+}
+
 }  // namespace
 
 size_t ctu_workspace_bytes(int64_t n, int elem) {
@@ -418,7 +744,7 @@ size_t ctu_workspace_bytes(int64_t n, int elem) {
 template <typename T>
 hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, int n_levels, const double *dt_dev,
                       const double *dh_dev, double gamma, double theta, T *fluxes, T *out, double *stats,
-                      unsigned long long *bad, void *work, hipStream_t s) {
+                      unsigned long long *bad, int variant, void *work, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     CtuArgs<T> P;
     P.in = in;
@@ -433,6 +759,12 @@ hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, int n_levels,
     P.gamma = gamma;
     P.theta = theta;
     P.n_groups = n;
+    P.work = nullptr;
+    P.counts = nullptr;
+    if (variant == 0) {
+        hipLaunchKernelGGL(ctu_fused<T>, dim3(unsigned(n)), dim3(FUSED_THREADS), 0, s, P);
+        return hipGetLastError();
+    }
     P.work = static_cast<T *>(work);
     // counters after the arrays, 256-byte aligned
     const size_t off = (size_t(n) * size_t(WORK_VALUES) * sizeof(T) + 255) & ~size_t(255);
@@ -445,9 +777,9 @@ hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, int n_levels,
 
 template hipError_t launch_ctu<float>(const float *, int64_t, const int8_t *, int, const double *,
                                       const double *, double, double, float *, float *, double *,
-                                      unsigned long long *, void *, hipStream_t);
+                                      unsigned long long *, int, void *, hipStream_t);
 template hipError_t launch_ctu<double>(const double *, int64_t, const int8_t *, int, const double *,
                                        const double *, double, double, double *, double *, double *,
-                                       unsigned long long *, void *, hipStream_t);
+                                       unsigned long long *, int, void *, hipStream_t);
 
 }  // namespace gamer

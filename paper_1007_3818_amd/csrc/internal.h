@@ -95,13 +95,14 @@ hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int
                        int n_levels, const double *dt_dev, const double *dh_dev, double gamma,
                        int order, T *work, T *out, hipStream_t s);
 
-// CTU coupling (ctu.hip): workspace bytes for n groups of elem-byte values, and
-// one step of padded groups
+// CTU coupling (ctu.hip): workspace bytes for n groups of elem-byte values (the
+// pipeline, variant 1), and one step of padded groups (variant 0: the fused
+// sweep, which takes no workspace)
 size_t ctu_workspace_bytes(int64_t n, int elem);
 template <typename T>
 hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, int n_levels, const double *dt_dev,
                       const double *dh_dev, double gamma, double theta, T *fluxes, T *out, double *stats,
-                      unsigned long long *bad, void *work, hipStream_t s);
+                      unsigned long long *bad, int variant, void *work, hipStream_t s);
 
 // two refinement levels (amr.hip)
 template <typename T>

@@ -253,15 +253,21 @@ def pack_periodic(state, gx, gy, gz, out=None):
 # ---- corner-transport-upwind coupling --------------------------------------
 
 def ctu_workspace(n_groups, dtype, device):
-    """A workspace tensor of the size gamer_ctu_solve_batched needs (256-byte aligned
-    by torch's allocator)."""
+    """A workspace tensor of the size the CTU pipeline (variant 1) needs
+    (256-byte aligned by torch's allocator)."""
     nbytes = _native.lib().gamer_ctu_workspace_bytes(int(n_groups), int(_f32(dtype)))
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 
 
+CTU_FUSED = 0     # one z-sweeping launch, intermediates on chip (default)
+CTU_PIPELINE = 1  # three launches through a workspace
+
+
 def ctu_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxes_out=None,
-                      group_stats=None, theta=None, work=None, bad_count=None):
-    """One step of padded groups with corner-transport-upwind coupling."""
+                      group_stats=None, theta=None, work=None, bad_count=None, variant=None):
+    """One step of padded groups with corner-transport-upwind coupling.
+    variant: CTU_FUSED (default) or CTU_PIPELINE, which takes `work` (allocated
+    here when None)."""
     f32 = _f32(groups_in.dtype)
     _need(groups_in, (NV, NP, NP, NP), groups_in.dtype, "groups_in")
     n = groups_in.shape[0]
@@ -273,17 +279,19 @@ def ctu_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxes_
     if group_stats is not None:
         _need(group_stats, (8,), torch.float64, "group_stats")
     _levels(level, dt_dev, dh_dev, n)
-    if work is None:
+    variant = CTU_FUSED if variant is None else int(variant)
+    if variant == CTU_PIPELINE and work is None:
         work = ctu_workspace(n, groups_in.dtype, groups_in.device)
-    if not isinstance(work, torch.Tensor) or not work.is_cuda or not work.is_contiguous():
+    if work is not None and (not isinstance(work, torch.Tensor) or not work.is_cuda
+                             or not work.is_contiguous()):
         raise ValueError("work must be a contiguous GPU tensor")
-    opts = _opts(theta, None, None, None, bad_count)
+    opts = _opts(theta, variant, None, None, bad_count)
     _stream()
     fn = _native.lib().gamer_ctu_solve_batched_f32 if f32 else _native.lib().gamer_ctu_solve_batched
     _native.check(fn(_ptr(groups_in), n, _ptr(level), _ptr(dt_dev), _ptr(dh_dev), dt_dev.numel(),
                      float(gamma), _ptr(fluxes_out), _ptr(out), _ptr(group_stats),
                      ctypes.byref(opts) if opts is not None else None, _ptr(work),
-                     work.numel() * work.element_size()))
+                     0 if work is None else work.numel() * work.element_size()))
     return out
 
 

@@ -153,16 +153,19 @@ def test_ctu_argument_errors(lib):
     need = lib.gamer_ctu_workspace_bytes(8, 0)
     assert need >= 8 * (6 * 5 * 18 ** 3 + 3 * 5 * 18 ** 3) * 8  # predicted states, transverse fluxes
     assert lib.gamer_ctu_workspace_bytes(0, 1) == 0
+    pipe = ctypes.byref(_native.GamerOpts(1.5, 1, 0, 0, 0))  # variant 1: the pipeline through a workspace
     for f in (lib.gamer_ctu_solve_batched, lib.gamer_ctu_solve_batched_f32):
-        assert f(P, -1, None, P, P, 1, 1.4, None, Q, None, None, W, need) == E
-        assert f(P, 8, None, P, P, 1, 1.0, None, Q, None, None, W, need) == E
-        assert f(None, 8, None, P, P, 1, 1.4, None, Q, None, None, W, need) == E
-        assert f(P, 8, None, None, P, 1, 1.4, None, Q, None, None, W, need) == E
-        assert f(P, 8, None, P, P, 0, 1.4, None, Q, None, None, W, need) == E
-        assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, None, None, need) == E
-        assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, None, W, 1000) == E
-        assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, None, ctypes.c_void_p(0x4010), need) == E
-        for bad in (_native.GamerOpts(1.5, 1, 0, 0, 0), _native.GamerOpts(1.5, 0, 8, 0, 0),
+        for o in (None, pipe):  # checks common to the fused sweep and the pipeline
+            assert f(P, -1, None, P, P, 1, 1.4, None, Q, None, o, W, need) == E
+            assert f(P, 8, None, P, P, 1, 1.0, None, Q, None, o, W, need) == E
+            assert f(None, 8, None, P, P, 1, 1.4, None, Q, None, o, W, need) == E
+            assert f(P, 8, None, None, P, 1, 1.4, None, Q, None, o, W, need) == E
+            assert f(P, 8, None, P, P, 0, 1.4, None, Q, None, o, W, need) == E
+        # the pipeline's workspace: missing, short, misaligned
+        assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, pipe, None, need) == E
+        assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, pipe, W, 1000) == E
+        assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, pipe, ctypes.c_void_p(0x4010), need) == E
+        for bad in (_native.GamerOpts(1.5, 2, 0, 0, 0), _native.GamerOpts(1.5, 0, 8, 0, 0),
                     _native.GamerOpts(1.5, 0, 0, 1, 0), _native.GamerOpts(3.0, 0, 0, 0, 0),
                     _native.GamerOpts(1.5, 0, 0, 0, 0, 0x1002)):
             assert f(P, 8, None, P, P, 1, 1.4, None, Q, None, ctypes.byref(bad), W, need) == E
