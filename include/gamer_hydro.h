@@ -293,10 +293,15 @@ int gamer_pack_periodic_f32(const float *state, int gx, int gy, int gz, float *p
  *  5. Roe fluxes at the 3 x 17 x 16^2 faces and the default full-step update.
  * HLLE fallbacks of steps 3 and 5 are counted in stat 7.  Arguments, layouts
  * and outputs as in gamer_hydro_solve_batched (padded input); opts may set
- * theta and bad_count_dev only.  work: device workspace of gamer_ctu_workspace_bytes(n, f32)
- * bytes, 256-byte aligned, owned by the caller; the call launches three
- * kernels and allocates nothing.  Errors as the batched step, plus a missing,
- * short or misaligned workspace and opts fields other than theta. */
+ * theta, bad_count_dev and variant: 0 (default) runs one z-sweeping launch
+ * with every intermediate on chip and ignores work (which may be NULL); 1 runs
+ * the three-launch pipeline, whose intermediates go through work: a device
+ * workspace of gamer_ctu_workspace_bytes(n, f32) bytes, 256-byte aligned,
+ * owned by the caller.  The two agree to rounding (FP64: about 1e-16 of each
+ * cell's update terms), with equal fallback counts.  Neither allocates.
+ * Errors as the batched step, plus opts fields other than theta, variant and
+ * bad_count_dev, a variant other than 0 or 1, and for variant 1 a missing,
+ * short or misaligned workspace. */
 size_t gamer_ctu_workspace_bytes(int64_t n_groups, int f32);
 int gamer_ctu_solve_batched(const double *groups_in, int64_t n_groups, const int8_t *level,
                             const double *dt_dev, const double *dh_dev, int n_levels, double gamma,
