@@ -125,6 +125,7 @@ __global__ __launch_bounds__(256) void group_stats_kernel(const T *__restrict__ 
 constexpr int RT = 1024;
 constexpr int RW = RT / 64;
 constexpr int RU = 4;  // groups per thread whose loads are in flight together
+constexpr int RL = 4;  // levels whose maxima are taken in the totals' pass
 
 template <int N>
 __device__ void block_fold(double (&x)[N], const bool (&is_max)[N], double (*red)[RW]) {
@@ -159,70 +160,90 @@ __global__ __launch_bounds__(RT) void reduce_kernel(const double *__restrict__ s
                                                     int n_levels, double cfl,
                                                     double *__restrict__ dt_out,
                                                     double *__restrict__ totals_out) {
-    __shared__ double red[7][RW];
+    // values folded: [0..4] dh^3-weighted sums of stats 0..4, [5..6] sums of
+    // stats 6..7, [7..7+RL) the signal-speed maxima of levels 0..RL-1
+    __shared__ double red[7 + RL][RW];
     const int t = threadIdx.x;
-    if (totals_out) {
-        // stats 0..4 weighted by dh^3 of the group's level, then stats 6 and 7
-        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-        const bool sum7[7] = {false, false, false, false, false, false, false};
-        // RU groups' loads are issued before any is folded (a single pass over
-        // 10^5 groups is otherwise one memory latency per group per thread); the
-        // fold order stays t, t + RT, t + 2 RT, ...
+    // one pass over the stats for the totals and, up to RL levels, the maxima;
+    // more levels take one further pass per level for their maxima
+    const bool tot = totals_out != nullptr;
+    const int lv_one = dt_out ? (n_levels <= RL ? n_levels : 0) : 0;
+    double x[7 + RL];
+    bool is_max[7 + RL];
+#pragma unroll
+    for (int q = 0; q < 7 + RL; ++q) {
+        x[q] = 0.0;
+        is_max[q] = q >= 7;
+    }
+    // RU groups' loads are issued before any is folded (a pass over 10^5
+    // groups is otherwise one memory latency per group per thread); each
+    // thread folds its groups in the order t, t + RT, t + 2 RT, ...
+    if (tot || lv_one > 0) {
         for (int64_t g0 = t; g0 < n; g0 += int64_t(RT) * RU) {
-            double s[RU][7], w[RU];
+            double s[RU][NSTAT], w[RU];
+            int lv[RU];
             bool ok[RU];
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
                 const int64_t g1 = g0 + int64_t(u) * RT;
                 ok[u] = g1 < n;
                 const int64_t g = ok[u] ? g1 : g0;  // a valid group to read; its values are not used
+                lv[u] = level ? int(level[g]) : 0;
                 double h = dh;
                 if (dh_dev) {
-                    const int lg = level ? int(level[g]) : 0;
                     // a level out of range is never used as an index; it makes the totals NaN
-                    h = (lg >= 0 && lg < n_levels) ? dh_dev[lg] : __builtin_nan("");
+                    h = (lv[u] >= 0 && lv[u] < n_levels) ? dh_dev[lv[u]] : __builtin_nan("");
                 }
                 w[u] = h * h * h;
                 const double *st = stats + g * NSTAT;
 #pragma unroll
-                for (int q = 0; q < 5; ++q) s[u][q] = st[q];
-                s[u][5] = st[6];
-                s[u][6] = st[7];
+                for (int q = 0; q < NSTAT; ++q) s[u][q] = st[q];
             }
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
                 if (!ok[u]) continue;
+                if (tot) {
 #pragma unroll
-                for (int q = 0; q < 5; ++q) acc[q] += w[u] * s[u][q];
-                acc[5] += s[u][5];
-                acc[6] += s[u][6];
+                    for (int q = 0; q < 5; ++q) x[q] += w[u] * s[u][q];
+                    x[5] += s[u][6];
+                    x[6] += s[u][7];
+                }
+#pragma unroll
+                for (int L = 0; L < RL; ++L)
+                    if (L < lv_one && lv[u] == L) x[7 + L] = max_nan(x[7 + L], s[u][5]);
             }
         }
-        block_fold(acc, sum7, red);
+        block_fold(x, is_max, red);
         if (t == 0) {
+            if (tot) {
 #pragma unroll
-            for (int q = 0; q < 7; ++q) totals_out[q] = acc[q];
+                for (int q = 0; q < 7; ++q) totals_out[q] = x[q];
+            }
         }
     }
     if (dt_out) {
         const bool max1[1] = {true};
         for (int L = 0; L < n_levels; ++L) {
             double m[1] = {0.0};
-            for (int64_t g0 = t; g0 < n; g0 += int64_t(RT) * RU) {
-                double sp[RU];
-                bool take[RU];
+            if (L < lv_one) {
+                m[0] = x[7 + (L < RL ? L : 0)];  // thread 0 holds the folded value
+            } else {
+                for (int64_t g0 = t; g0 < n; g0 += int64_t(RT) * RU) {
+                    double sp[RU];
+                    bool take[RU];
 #pragma unroll
-                for (int u = 0; u < RU; ++u) {
-                    const int64_t g1 = g0 + int64_t(u) * RT;
-                    const int64_t g = g1 < n ? g1 : g0;
-                    take[u] = g1 < n && (level ? int(level[g]) : 0) == L;
-                    sp[u] = stats[g * NSTAT + 5];
+                    for (int u = 0; u < RU; ++u) {
+                        const int64_t g1 = g0 + int64_t(u) * RT;
+                        const int64_t g = g1 < n ? g1 : g0;
+                        take[u] = g1 < n && (level ? int(level[g]) : 0) == L;
+                        sp[u] = stats[g * NSTAT + 5];
+                    }
+#pragma unroll
+                    for (int u = 0; u < RU; ++u)
+                        if (take[u]) m[0] = max_nan(m[0], sp[u]);
                 }
-#pragma unroll
-                for (int u = 0; u < RU; ++u)
-                    if (take[u]) m[0] = max_nan(m[0], sp[u]);
+                block_fold(m, max1, red);
             }
-            block_fold(m, max1, red);
             if (t == 0) {
                 const double hL = dh_dev ? dh_dev[L] : dh;
                 // NaN when a group of the level has a non-physical cell
