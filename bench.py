@@ -75,6 +75,34 @@ GAMMA = 5.0 / 3.0
 CFL = 0.5
 
 
+SOLVER_SOURCES = ("solver.hip", "euler.h", "device_math.h", "internal.h")
+
+
+def read_traffic(tag, variant, grid, n_groups):
+    """HBM bytes per launch of the batched solver from the committed counter
+    summary, when it was taken on the current kernel sources, batch size and
+    launch shape; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "solve_kernel_traffic_1024.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in SOLVER_SOURCES:
+        with open(os.path.join(ROOT, "paper_1007_3818_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    for line in open(path):
+        if " = " in line:
+            k, v = line.strip().split(" = ", 1)
+            vals[k] = v
+    if vals.get("solver_sources_sha256_16") != h.hexdigest()[:16]:
+        return None
+    if vals.get("n_groups") != str(n_groups) or vals.get("shape") != f"{variant} {grid}":
+        return None
+    v = vals.get(f"bytes_per_launch_{tag}")
+    return float(v) if v else None
+
+
 def progress(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -149,8 +177,9 @@ def bench_dtype(tag, state, g, dh, steps, warmup, workload, shape=None, pick=Non
         "peak": PEAK[tag] / 1e12,
         "unit": "TFLOP/s",
         "frac": flops / (k_ms * 1e-3) / PEAK[tag],
-        # HBM bytes from counters: not taken on this kernel revision
-        "traffic": None,
+        # HBM bytes per launch from FETCH_SIZE / WRITE_SIZE counter runs, scaled by
+        # a plain copy's counters; None unless taken on these sources and shape
+        "traffic": read_traffic(tag, variant, grid, n_groups),
         # the instantiation as rocprofv3 names it: <storage, arithmetic, threads,
         # waves per SIMD, periodic input, characteristic limiting>
         "kernel": "solve_kernel<{0}, {0}, {1}, {2}, false, false>".format(
@@ -664,6 +693,40 @@ def accuracy(samples, g, dh):
     return out
 
 
+def counter_pass(args, dev):
+    """The launches a counter run measures, with few other dispatches."""
+    import torch
+    from paper_1007_3818_amd import hydro, workloads
+
+    if args.dtype == "both":
+        raise SystemExit("--counter-pass takes --dtype f32 or f64")
+    n, kmax = (256, 4) if args.workload == 2 else (1024, 8)
+    g = n // 16
+    progress(f"generating workload {args.workload} on the host")
+    st, dh = workloads.smooth_modes(n=n, kmax=kmax, workload=args.workload, device="cpu")
+    st = (st.float() if args.dtype == "f32" else st).to(dev)
+    progress("plain 1 GiB device copy")
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    pad = hydro.pack_periodic(st, g, g, g)
+    stats = torch.empty((g ** 3, 8), dtype=torch.float64, device=dev)
+    dh_dev = torch.full((1,), dh, dtype=torch.float64, device=dev)
+    dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
+    hydro.group_stats(st, GAMMA, out=stats)
+    hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev)
+    del st
+    out = torch.empty((g ** 3, 5, 16, 16, 16), dtype=pad.dtype, device=dev)
+    v = args.variant or 0
+    for k in range(args.counter_pass):
+        hydro.hydro_solve_batched(pad, None, dt_dev, dh_dev, GAMMA, out=out, group_stats=stats, variant=v,
+                                  grid=args.grid)
+        torch.cuda.synchronize()
+        progress(f"solve {k + 1} of {args.counter_pass}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -682,6 +745,11 @@ def main():
     ap.add_argument("--no-levels", action="store_true", help="skip the three-level and high-contrast batches")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for counter scaling)")
+    ap.add_argument("--counter-pass", type=int, default=0, metavar="N",
+                    help="for a counter run: generate the workload on the host (a counter run serialises "
+                         "every dispatch, and the device generator issues thousands), copy it over, run a "
+                         "plain 1 GiB device copy, then N batched solves of --dtype at --variant/--grid, "
+                         "and exit without timing")
     ap.add_argument("--variant", type=int, default=None,
                     help="use this compiled solver variant (with --grid) instead of tuning")
     ap.add_argument("--grid", type=int, default=0, help="launch grid with --variant (0: one per group)")
@@ -697,6 +765,9 @@ def main():
 
     dev = torch.device("cuda:0")
     progress("start")
+    if args.counter_pass > 0:
+        counter_pass(args, dev)
+        return
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
         b = torch.empty_like(a)
