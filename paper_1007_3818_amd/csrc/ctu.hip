@@ -3,9 +3,11 @@
 // transverse Roe fluxes, then the final Roe fluxes and the same full-step
 // update as the default path.  Two implementations:
 //
-// ctu_fused (variant 0, the default): one work-group per group sweeping z with
-// every intermediate on chip.  Thread t < 324 owns the column (i, j) of the
-// 18 x 18 square of cells -1..16; step s (planes s = -1..16):
+// ctu_fused (variant 0, the default): 384 threads per group sweeping z with
+// every intermediate on chip (two groups side by side per work-group in
+// float, so that the work-group's 12 waves sit three to a SIMD).  Thread
+// t < 324 of a group owns the column (i, j) of the 18 x 18 square of cells
+// -1..16; step s (planes s = -1..16):
 //   A  the z predictor of plane s, the transverse z flux between planes s - 1
 //      and s (registers: this thread holds the plus-z state below), the
 //      corrections of plane s - 1's x and y states (they need that flux and the
@@ -445,20 +447,23 @@ struct FusedLds {
     };
 };
 
-// Work-group size: one thread per cell of an 18 x 18 plane (324 of 384 busy).
-// LDS: 70 KB in float (two work-groups per CU, three waves per SIMD), 140 KB in
-// double (one work-group per CU).
+// Threads per group: one per cell of an 18 x 18 plane (324 of 384 busy).
+// LDS per group: 70 KB in float, 140 KB in double.  A work-group sweeps
+// FusedShape::groups groups side by side, so that its waves spread evenly over
+// the CU's four SIMDs (a lone 6-wave work-group puts two waves on two SIMDs
+// and one on the others): float two groups (12 waves, 140 KB, three waves per
+// SIMD), double one.
 constexpr int FUSED_THREADS = 384;
 
 template <typename T>
-struct FusedWaves;
+struct FusedShape;
 template <>
-struct FusedWaves<float> {
-    static constexpr int waves = 3;
+struct FusedShape<float> {
+    static constexpr int waves = 3, groups = 2;
 };
 template <>
-struct FusedWaves<double> {
-    static constexpr int waves = 2;
+struct FusedShape<double> {
+    static constexpr int waves = 2, groups = 1;
 };
 
 // u = p - hdt (a + b), or p itself (and false) when that leaves the physical
@@ -483,14 +488,23 @@ __device__ __forceinline__ bool correct_state(const T p[NV], const T a[NV], cons
 }
 
 template <typename T>
-__global__ __attribute__((amdgpu_flat_work_group_size(FUSED_THREADS, FUSED_THREADS),
-                          amdgpu_waves_per_eu(FusedWaves<T>::waves, 8)))
+__global__ __attribute__((amdgpu_flat_work_group_size(FUSED_THREADS * FusedShape<T>::groups,
+                                                      FUSED_THREADS * FusedShape<T>::groups),
+                          amdgpu_waves_per_eu(FusedShape<T>::waves, 8)))
 void ctu_fused(CtuArgs<T> P) {
     constexpr int NT = FUSED_THREADS;
-    static_assert(NT >= CE * CE, "one thread per cell of a plane");
-    __shared__ FusedLds<T> S;
-    const int64_t g = blockIdx.x;
-    if (g >= P.n_groups) return;
+    static_assert(NT >= CE * CE && NT % 64 == 0, "one thread per cell of a plane, whole waves");
+    constexpr int G = FusedShape<T>::groups;
+    __shared__ FusedLds<T> SS[G];
+    const int half = G > 1 ? int(threadIdx.x) / NT : 0;
+    FusedLds<T> &S = SS[half];
+    const int64_t g_raw = int64_t(blockIdx.x) * G + half;
+    if (G == 1 && g_raw >= P.n_groups) return;
+    // with several groups per work-group the last slot may lie past the batch:
+    // its threads then take no cell (they read group 0's input and write
+    // nothing) but still meet every barrier
+    const bool live = G == 1 || g_raw < P.n_groups;
+    const int64_t g = live ? g_raw : 0;
     const Consts<T> c = make_consts<T>(P.gamma, P.theta);
     double dt, dh;
     const bool lev_ok = group_dt(P, g, dt, dh);
@@ -498,9 +512,9 @@ void ctu_fused(CtuArgs<T> P) {
     const double dtdh = dt / dh;
     const T *U = P.in + g * GIN;
     T *out = P.out + g * GOUT;
-    const int t = threadIdx.x;
-    if (!lev_ok && P.bad && t == 0) atomicAdd(P.bad + 1, 1ull);
-    const bool mine = t < CE * CE;
+    const int t = threadIdx.x - half * NT;
+    if (live && !lev_ok && P.bad && t == 0) atomicAdd(P.bad + 1, 1ull);
+    const bool mine = live && t < CE * CE;
     const int i = t % CE - 1, j = t / CE - 1;  // this thread's column, meaningful when mine
     const int ii = i + NG, jj = j + NG;        // its padded position
     const bool in_i = i >= 0 && i < NI, in_j = j >= 0 && j < NI;
@@ -773,7 +787,7 @@ void ctu_fused(CtuArgs<T> P) {
         st[6] = double(n_pred);
         st[7] = double(n_roe);
         __syncthreads();  // the ring and the plane arrays are no longer read
-        block_reduce_stats<NT>(st, S.red, P.stats + g * NSTAT);
+        block_reduce_stats<NT>(st, S.red, live ? P.stats + g * NSTAT : nullptr, t);
     }
 }
 
@@ -805,7 +819,8 @@ hipError_t launch_ctu(const T *in, int64_t n, const int8_t *level, int n_levels,
     P.work = nullptr;
     P.counts = nullptr;
     if (variant == 0) {
-        hipLaunchKernelGGL(ctu_fused<T>, dim3(unsigned(n)), dim3(FUSED_THREADS), 0, s, P);
+        constexpr int G = FusedShape<T>::groups;
+        hipLaunchKernelGGL(ctu_fused<T>, dim3(unsigned((n + G - 1) / G)), dim3(FUSED_THREADS * G), 0, s, P);
         return hipGetLastError();
     }
     P.work = static_cast<T *>(work);

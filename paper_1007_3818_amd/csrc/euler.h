@@ -297,12 +297,14 @@ __device__ __forceinline__ bool roe_dir(const T UL[NV], const T UR[NV], const Co
     return fb;
 }
 
-// Fixed-order reduction of NSTAT doubles per thread over NTHREADS threads:
-// stats 0..4 and 6..7 are summed, stat 5 is a maximum that keeps NaN.  Lane 0
-// of wave 0 writes the result.  `red` must hold NTHREADS * NSTAT doubles of LDS.
+// Fixed-order reduction of NSTAT doubles per thread over NTHREADS threads
+// (thread index t, 0 .. NTHREADS - 1, NTHREADS a multiple of 64 when the
+// work-group holds several such sets): stats 0..4 and 6..7 are summed, stat 5
+// is a maximum that keeps NaN.  Thread 0 writes the result to dst (if not
+// null).  `red` must hold NTHREADS * NSTAT doubles of LDS.
 template <int NTHREADS>
-__device__ __forceinline__ void block_reduce_stats(double st[NSTAT], double *red, double *dst) {
-    const int t = threadIdx.x;
+__device__ __forceinline__ void block_reduce_stats(double st[NSTAT], double *red, double *dst,
+                                                   int t = threadIdx.x) {
 #pragma unroll
     for (int q = 0; q < NSTAT; ++q) red[q * NTHREADS + t] = st[q];
     __syncthreads();
@@ -325,7 +327,7 @@ __device__ __forceinline__ void block_reduce_stats(double st[NSTAT], double *red
                 acc[q] = (q == 5) ? max_nan(acc[q], b) : acc[q] + b;
             }
         }
-        if (t == 0) {
+        if (t == 0 && dst) {
 #pragma unroll
             for (int q = 0; q < NSTAT; ++q) dst[q] = acc[q];
         }
