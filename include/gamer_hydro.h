@@ -39,7 +39,9 @@
  *    current stream (gamer_set_stream; default: the null stream).  Errors a
  *    kernel meets later surface at the next synchronising call.
  *  - Return value: GAMER_OK (0) or a negative code; gamer_last_error() then
- *    holds a message (per host thread).  n_groups == 0 is a successful no-op.
+ *    holds a message (per host thread).  n_groups == 0 is a successful no-op
+ *    (gamer_step_reduce then writes the reduction over no groups: dt = +inf
+ *    for every level, totals 0).
  *  - Inputs and outputs must not overlap.
  *  - Non-physical intermediate states are not errors: the solver falls back
  *    (first-order prediction for the cell, HLLE for the face) and counts them

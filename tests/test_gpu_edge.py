@@ -1,0 +1,123 @@
+"""Degenerate batches through the C ABI.
+
+  * Zero groups (or zero records) is a successful no-op for every entry point:
+    each call returns GAMER_OK and leaves every output buffer as it was.  The
+    one exception is documented: gamer_step_reduce over no groups writes the
+    empty reduction (dt = +inf for every level, totals 0).
+  * One group: the smallest ragged batch.  The float CTU sweep puts two groups
+    in one work-group, so a one-group (or odd) batch runs with an empty second
+    half; the result must still match the oracle and the pipeline variant.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1007_3818_amd import _native, hydro, workloads as W
+from parity import l1_rel, state_close, update_terms
+
+pytestmark = pytest.mark.gpu
+G53 = 5.0 / 3.0
+SENTINEL = 7.25
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def test_zero_groups_every_entry_point(gpu):
+    L = _native.lib()
+    d = torch.full((4096,), SENTINEL, dtype=torch.float64, device=gpu)   # inputs and outputs, double
+    f = torch.full((4096,), SENTINEL, dtype=torch.float32, device=gpu)   # inputs and outputs, float
+    st = torch.full((64,), SENTINEL, dtype=torch.float64, device=gpu)    # stats, dt, sums, accumulators
+    lev = torch.zeros(8, dtype=torch.int8, device=gpu)
+    par = torch.zeros(8, dtype=torch.int64, device=gpu)
+    nbad = torch.zeros(4, dtype=torch.int32, device=gpu)
+    dt_dev = torch.tensor([1e-3], dtype=torch.float64, device=gpu)
+    dh_dev = torch.tensor([1e-2], dtype=torch.float64, device=gpu)
+    work = torch.full((1024,), 3, dtype=torch.uint8, device=gpu)
+    opts = [_native.GamerOpts(theta=1.5, variant=v, grid=0, limiting=0, reserved=0, bad_count_dev=None)
+            for v in (0, 1)]
+    P, D, F, S = _p, _p(d), _p(f), _p(st)
+    calls = {
+        "gamer_hydro_solve": (D, 0, 1e-3, 1e-2, G53, D, D),
+        "gamer_hydro_solve_f32": (F, 0, 1e-3, 1e-2, G53, F, F),
+        "gamer_hydro_solve_batched": (D, 0, P(lev), P(dt_dev), P(dh_dev), 1, G53, D, D, S, None, None),
+        "gamer_hydro_solve_batched_f32": (F, 0, P(lev), P(dt_dev), P(dh_dev), 1, G53, F, F, S, None, None),
+        "gamer_hydro_solve_batched_mixed": (D, 0, P(lev), P(dt_dev), P(dh_dev), 1, G53, D, D, S, None, None),
+        "gamer_group_stats": (D, 0, G53, S),
+        "gamer_group_stats_f32": (F, 0, G53, S),
+        "gamer_cfl_dt": (D, 0, 1e-2, G53, 0.5, S, 1),
+        "gamer_cfl_dt_f32": (F, 0, 1e-2, G53, 0.5, S, 1),
+        "gamer_cfl_dt_noalloc": (D, 0, 1e-2, G53, 0.5, S),
+        "gamer_conserved_sums": (D, 0, 1e-2, S, 1),
+        "gamer_conserved_sums_f32": (F, 0, 1e-2, S, 1),
+        "gamer_ctu_solve_batched": (D, 0, P(lev), P(dt_dev), P(dh_dev), 1, G53, D, D, S,
+                                    ctypes.byref(opts[0]), None, 0),
+        "gamer_ctu_solve_batched_f32": (F, 0, P(lev), P(dt_dev), P(dh_dev), 1, G53, F, F, S,
+                                        ctypes.byref(opts[0]), None, 0),
+        "gamer_rtvd_solve_batched": (D, 0, P(lev), P(dt_dev), P(dh_dev), 1, G53, 0, P(work), 1024, D),
+        "gamer_rtvd_solve_batched_f32": (F, 0, P(lev), P(dt_dev), P(dh_dev), 1, G53, 1, P(work), 1024, F),
+        "gamer_flux_accumulate": (D, 0, P(dt_dev), 1, S),
+        "gamer_flux_accumulate_f32": (F, 0, P(dt_dev), 0, S),
+        "gamer_flux_correct": (D, 0, D, S, 0, P(par), 0, P(dt_dev), P(dh_dev), P(nbad)),
+        "gamer_flux_correct_f32": (F, 0, F, S, 0, P(par), 0, P(dt_dev), P(dh_dev), P(nbad)),
+        "gamer_restrict": (D, P(par), 0, D, 0, P(nbad)),
+        "gamer_restrict_f32": (F, P(par), 0, F, 0, P(nbad)),
+    }
+    # the pipeline CTU variant with no groups needs no workspace either
+    calls["gamer_ctu_solve_batched#pipeline"] = (D, 0, P(lev), P(dt_dev), P(dh_dev), 1, G53, D, D, S,
+                                                 ctypes.byref(opts[1]), None, 0)
+    for name, args in calls.items():
+        rc = getattr(L, name.split("#")[0])(*args)
+        assert rc == _native.GAMER_OK, (name, rc, L.gamer_last_error())
+    torch.cuda.synchronize()
+    assert bool((d == SENTINEL).all()) and bool((f == SENTINEL).all()) and bool((st == SENTINEL).all())
+    assert int(nbad.abs().sum()) == 0 and bool((work == 3).all()) and bool((lev == 0).all())
+    print(f"[edge] {len(calls)} entry points with no groups: all GAMER_OK, outputs untouched", flush=True)
+
+    # the reduction over no groups: dt +inf per level, totals 0
+    dts = torch.full((3,), SENTINEL, dtype=torch.float64, device=gpu)
+    tot = torch.full((7,), SENTINEL, dtype=torch.float64, device=gpu)
+    dhs = torch.tensor([1.0, 0.5, 0.25], dtype=torch.float64, device=gpu)
+    rc = L.gamer_step_reduce(S, 0, None, P(dhs), 3, 0.5, P(dts), P(tot))
+    assert rc == _native.GAMER_OK
+    assert dts.cpu().tolist() == [float("inf")] * 3
+    assert tot.cpu().tolist() == [0.0] * 7
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_one_group_ctu_both_variants(gpu, dtype):
+    """A batch of one group (the float sweep's work-group then holds one live
+    group and one empty half) against the oracle: FP64 per cell within 1e-12,
+    FP32 within 1e-5 in L1 per variable (oracle on the float-rounded input);
+    the fused sweep and the pipeline agree per cell (relative to the cell's
+    update terms) within 1e-13 / 1e-5 with equal fallback counts."""
+    st, dh = W.smooth_modes(n=16, kmax=1, workload=2)
+    s = st.to(dtype)
+    host = s.double().numpy()
+    dt = oracle.cfl_dt(host, dh, G53, 0.4)
+    pad_h = oracle.pack_periodic(host, 1, 1, 1)
+    ref, _, cnt = oracle.hydro_solve(pad_h, dt, dh, G53, coupling="ctu")
+    pad = hydro.pack_periodic(s.to(gpu), 1, 1, 1)
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device=gpu)
+    dh_dev = torch.tensor([dh], dtype=torch.float64, device=gpu)
+    res = []
+    for v in (hydro.CTU_FUSED, hydro.CTU_PIPELINE):
+        stats = torch.full((1, 8), SENTINEL, dtype=torch.float64, device=gpu)
+        out = hydro.ctu_solve_batched(pad, None, dt_dev, dh_dev, G53, group_stats=stats, variant=v)
+        res.append((out.cpu().double().numpy(), stats.cpu().numpy()))
+    (a, sa), (b, sb) = res
+    if dtype == torch.float64:
+        state_close(a, ref, 1e-12, "ctu one group fp64 fused")
+    else:
+        l1 = l1_rel(a, ref)
+        print(f"[parity] ctu one group fp32 fused: L1 per variable {l1}", flush=True)
+        assert np.all(l1 < 1e-5), l1
+    terms = update_terms(pad_h, dt, dh)
+    state_close(a, b, 1e-13 if dtype == torch.float64 else 1e-5, f"ctu one group {dtype} fused vs pipeline",
+                terms=terms)
+    assert (int(sa[0, 6]), int(sa[0, 7])) == cnt and np.array_equal(sa[:, 6:], sb[:, 6:])
+    assert np.isfinite(sa).all()
