@@ -177,9 +177,15 @@ __device__ __forceinline__ void hlle(const T L[NV], const T R[NV], T uL, T pL, T
 // rho, (rho* c*)^2 = gq Q*), and the square roots are taken only on lanes where
 // the fix is active or HLLE is used; in float the square root is one hardware
 // instruction and the speeds are formed directly.
-template <typename T>
+//
+// TWICE: return 2F instead of F.  Every component of F is half of a sum, and
+// halving is exact, so a caller that scales its use of the flux by 1/2 (the
+// update's dt/dh, the flux planes it stores) gets the same values bitwise
+// without the five multiplications.
+template <typename T, bool TWICE = false>
 __device__ __forceinline__ bool roe(const T L[NV], const T R[NV], const Consts<T> &c, T F[NV]) {
     const T h = c.half;
+    const T hf = TWICE ? T(1) : h;  // the flux sums' factor
     const T qL = rsq(L[0]), qR = rsq(R[0]);
     const T irL = qL * qL, irR = qR * qR;
     const T uL = L[1] * irL, vL = L[2] * irL, wL = L[3] * irL;
@@ -198,6 +204,10 @@ __device__ __forceinline__ bool roe(const T L[NV], const T R[NV], const Consts<T
     const T a2 = c.gm1 * (H - h * q2);
     if (!(a2 > T(0))) {
         hlle(L, R, uL, pL, uR, pR, uL - sqrt_(c2L), uR + sqrt_(c2R), F);
+        if (TWICE) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m) F[m] *= T(2);
+        }
         return true;
     }
     const T ia = rsq(a2);
@@ -221,6 +231,10 @@ __device__ __forceinline__ bool roe(const T L[NV], const T R[NV], const Consts<T
     const T QR = T(2) * Rs[0] * Rs[4] - (Rs[1] * Rs[1] + Rs[2] * Rs[2] + Rs[3] * Rs[3]);
     if (!(Ls[0] > T(0) && QL > T(0) && Rs[0] > T(0) && QR > T(0))) {
         hlle(L, R, uL, pL, uR, pR, fmin(uL - sqrt_(c2L), u - a), fmax(uR + sqrt_(c2R), u + a), F);
+        if (TWICE) {
+#pragma unroll
+            for (int m = 0; m < NV; ++m) F[m] *= T(2);
+        }
         return true;
     }
     // Harten-Hyman: wave 1 between L (speed uL - cL) and L* (speed (m* - rho* c*)/rho*),
@@ -271,24 +285,24 @@ __device__ __forceinline__ bool roe(const T L[NV], const T R[NV], const Consts<T
     // the sum of the three amplitudes once
     const T c1 = al1 * ab1, c2 = al2 * ab2, c3 = al3 * ab2, c4 = al4 * ab2, c5 = al5 * ab5;
     const T s125 = (c1 + c2) + c5;
-    F[0] = h * ((L[1] + R[1]) - s125);
-    F[1] = h * ((L[1] * uL + pL + R[1] * uR + pR) - ((c1 * (u - a) + c2 * u) + c5 * (u + a)));
-    F[2] = h * ((L[2] * uL + R[2] * uR) - (s125 * v + c3));
-    F[3] = h * ((L[3] * uL + R[3] * uR) - (s125 * w + c4));
-    F[4] = h * (((L[4] + pL) * uL + (R[4] + pR) * uR) -
-                ((((c1 * (H - ua) + c2 * (h * q2)) + c3 * v) + c4 * w) + c5 * (H + ua)));
+    F[0] = hf * ((L[1] + R[1]) - s125);
+    F[1] = hf * ((L[1] * uL + pL + R[1] * uR + pR) - ((c1 * (u - a) + c2 * u) + c5 * (u + a)));
+    F[2] = hf * ((L[2] * uL + R[2] * uR) - (s125 * v + c3));
+    F[3] = hf * ((L[3] * uL + R[3] * uR) - (s125 * w + c4));
+    F[4] = hf * (((L[4] + pL) * uL + (R[4] + pR) * uR) -
+                 ((((c1 * (H - ua) + c2 * (h * q2)) + c3 * v) + c4 * w) + c5 * (H + ua)));
     return false;
 }
 
-// Roe flux along direction D for unrotated conserved states.
-template <int D, typename T>
+// Roe flux along direction D for unrotated conserved states (2F with TWICE).
+template <int D, bool TWICE = false, typename T>
 __device__ __forceinline__ bool roe_dir(const T UL[NV], const T UR[NV], const Consts<T> &c,
                                         T F[NV]) {
     constexpr int n = 1 + D, t1 = 1 + (D + 1) % 3, t2 = 1 + (D + 2) % 3;
     const T L[NV] = {UL[0], UL[n], UL[t1], UL[t2], UL[4]};
     const T R[NV] = {UR[0], UR[n], UR[t1], UR[t2], UR[4]};
     T Fr[NV];
-    const bool fb = roe(L, R, c, Fr);
+    const bool fb = roe<T, TWICE>(L, R, c, Fr);
     F[0] = Fr[0];
     F[n] = Fr[1];
     F[t1] = Fr[2];

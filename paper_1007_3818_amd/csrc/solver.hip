@@ -143,6 +143,7 @@ void solve_kernel(SolveParams<S_> P) {
             if (P.bad && t == 0) atomicAdd(P.bad + 1, 1ull);
         }
         const double dtdh = dt / dh;
+        const double hdtdh = 0.5 * dtdh;  // the Roe fluxes below are kept doubled (2F)
 
         // ---- where padded cell (ip, jp, kp) of this group lives in the input ----
         // Padded input: the group's own padded block.  Periodic input: the cell at
@@ -400,11 +401,11 @@ void solve_kernel(SolveParams<S_> P) {
             T fzn[NV];
             auto solve_z = [&]() {
                 if (inner && k >= 0) {
-                    n_roe += roe_dir<2>(zp, zm, c, fzn);
+                    n_roe += roe_dir<2, true>(zp, zm, c, fzn);
                     if (P.flux && (k & 7) == 0) {
                         S_ *dst = P.flux + g * GFLX + ((2 * 3 + (k >> 3)) * NV) * NINNER + jj * NI + ii;
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(fzn[v]);
+                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(c.half * fzn[v]);
                     }
                 }
             };
@@ -438,13 +439,13 @@ void solve_kernel(SolveParams<S_> P) {
                         UL[v] = S.sx[v][row][f];
                         UR[v] = round == 0 ? xm[v] : S.rf[0][v][row];
                     }
-                    n_roe += roe_dir<0>(UL, UR, c, F);
+                    n_roe += roe_dir<0, true>(UL, UR, c, F);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) S.sx[v][row][f] = F[v];
                     if (P.flux && (f & 7) == 0) {
                         S_ *dst = P.flux + g * GFLX + ((0 * 3 + (f >> 3)) * NV) * NINNER + k * NI + row;
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(F[v]);
+                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(c.half * F[v]);
                     }
                 }
                 // y faces: face cj of each interior cell, then face 16 of each column
@@ -466,13 +467,13 @@ void solve_kernel(SolveParams<S_> P) {
                         UL[v] = S.sy[v][f][col];
                         UR[v] = round == 0 ? ym[v] : S.rf[1][v][col];
                     }
-                    n_roe += roe_dir<1>(UL, UR, c, F);
+                    n_roe += roe_dir<1, true>(UL, UR, c, F);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) S.sy[v][f][col] = F[v];
                     if (P.flux && (f & 7) == 0) {
                         S_ *dst = P.flux + g * GFLX + ((1 * 3 + (f >> 3)) * NV) * NINNER + k * NI + col;
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(F[v]);
+                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(c.half * F[v]);
                     }
                 }
             }
@@ -506,7 +507,7 @@ void solve_kernel(SolveParams<S_> P) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         const double dfz = double(fzn[v]) - double(fz[v]);
-                        const double r = double(uold[v]) - dtdh * (S.dxy[v][t] + dfz);
+                        const double r = double(uold[v]) - hdtdh * (S.dxy[v][t] + dfz);
                         const S_ o = S_(r);
                         at(dst + v * NI * NINNER, unsigned(t)) = o;
                         un[v] = T(o);
