@@ -239,3 +239,50 @@ def test_two_level_step_against_oracle(gpu, dtype):
             got = got.cpu().double().numpy()
             l1 = np.abs(got - want).sum(axis=(0, 2, 3, 4)) / np.abs(want).sum(axis=(0, 2, 3, 4))
             assert np.all(l1 < 1e-5), l1
+
+
+def sphere_layout(g, radius=0.3):
+    """The refined sphere the benchmark times on a grid of g^3 coarse groups:
+    every 8^3 patch whose centre lies within `radius` of the box size from the
+    box centre becomes a fine group."""
+    npch = 2 * g
+    c = (np.arange(npch) + 0.5) / npch - 0.5
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    sel = np.argwhere(X ** 2 + Y ** 2 + Z ** 2 < radius ** 2)  # (pz, py, px)
+    patches = [((px // 2) + g * ((py // 2) + g * (pz // 2)), (px % 2) + 2 * (py % 2) + 4 * (pz % 2))
+               for pz, py, px in sel]
+    return amr.refine(g, g, g, patches)
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_bench_size_sphere(gpu, dtype):
+    """Flux correction and restriction at the size the benchmark times: the
+    256^3 grid (4096 coarse groups) with the refined sphere's 3648 fine groups
+    and 1704 face records, each on the same input state, whole arrays against
+    the oracle (on the same dtype-rounded inputs).  Coarse state: the smooth-mode flow; fine state:
+    independent random physical states; fluxes: seeded random values."""
+    g = 16
+    parent, faces = sphere_layout(g)
+    assert (len(parent), len(faces)) == (3648, 1704)
+    st, dh = W.smooth_modes(n=256)
+    r = np.random.default_rng(11)
+    coarse = st.to(dtype)
+    fine = phys(r, len(parent)).to(dtype)
+    cfl = torch.from_numpy(0.1 * r.standard_normal((g ** 3, 3, 3, 5, 16, 16))).to(dtype)
+    acc = torch.from_numpy(1e-3 * r.standard_normal((len(parent), 3, 3, 5, 16, 16)))
+    dt = 0.05 * dh
+    want = oamr.flux_correct(coarse.double().numpy(), cfl.double().numpy(), acc.numpy(), faces, dt, dh)
+    c = coarse.to(gpu)
+    bad = torch.zeros(1, dtype=torch.int32, device=gpu)
+    hydro.flux_correct(c, cfl.to(gpu), acc.to(gpu), amr.faces_to_device(faces, gpu), dev1(dt, gpu),
+                       dev1(dh, gpu), n_bad=bad)
+    f64 = dtype == torch.float64
+    state_close(c.cpu().numpy(), want, 1e-12 if f64 else 1e-6, f"sphere flux correct {dtype}")
+    del cfl, acc
+    # restriction of the same input state, checked on its own
+    want2 = oamr.restrict(coarse.double().numpy(), fine.double().numpy(), parent)
+    c = coarse.to(gpu)
+    hydro.restrict(fine.to(gpu), torch.from_numpy(parent).to(gpu), c, n_bad=bad)
+    state_close(c.cpu().numpy(), want2, 1e-14 if f64 else 1e-7, f"sphere restrict {dtype}")
+    assert int(bad.item()) == 0

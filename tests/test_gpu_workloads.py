@@ -134,3 +134,38 @@ def test_workload5_sampled_full_size(gpu):
     gp32 = hydro.pack_periodic(s32, g, g, g)
     out32 = hydro.hydro_solve(gp32, dt, dh, G53)
     state_close(out32[idx].cpu().numpy(), ref32, 1e-5, "workload 5 fp32")
+
+
+@pytest.mark.timeout(400)
+def test_workload5_sampled_periodic_and_mixed(gpu):
+    """Workload 5 (1024^3, 262144 groups) through the fused periodic step (ghost
+    cells read in place) as the benchmark times it: FP64, FP64 state with FP32
+    arithmetic, and FP32.  The same sixteen sampled groups against the oracle,
+    which pads them itself: FP64 per cell within 1e-12; the mixed and FP32
+    steps per cell within 1e-5 (the FP32 one against the oracle on the
+    float-rounded state)."""
+    n = 1024
+    g = n // 16
+    st, dh = W.smooth_modes(n=n, kmax=8, workload=5, device=gpu)
+    dt = 0.1 * dh
+    rng = np.random.default_rng(5)
+    corners = [x + g * (y + g * z) for x in (0, g - 1) for y in (0, g - 1) for z in (0, g - 1)]
+    pick = sorted(set(corners) | set(int(x) for x in rng.choice(g ** 3, size=8, replace=False)))
+    idx = torch.as_tensor(pick, device=gpu)
+    dt_dev = torch.tensor([dt], dtype=torch.float64, device=gpu)
+    dh_dev = torch.tensor([dh], dtype=torch.float64, device=gpu)
+    ref, _, cnt = oracle.hydro_solve(oracle.pack_periodic_subset(st, g, g, g, pick), dt, dh, G53)
+    assert cnt == (0, 0)
+    out = torch.empty_like(st)
+    hydro.hydro_solve_periodic(st, g, g, g, dt_dev, dh_dev, G53, out=out)
+    state_close(out[idx].cpu().numpy(), ref, 1e-12, "workload 5 periodic fp64")
+    hydro.hydro_solve_periodic(st, g, g, g, dt_dev, dh_dev, G53, out=out, compute=torch.float32)
+    state_close(out[idx].cpu().numpy(), ref, 1e-5, "workload 5 periodic fp64 state, fp32 arithmetic")
+    del out
+    s32 = st.float()
+    del st
+    torch.cuda.empty_cache()
+    ref32, _, _ = oracle.hydro_solve(oracle.pack_periodic_subset(s32, g, g, g, pick), dt, dh, G53)
+    out32 = torch.empty_like(s32)
+    hydro.hydro_solve_periodic(s32, g, g, g, dt_dev, dh_dev, G53, out=out32)
+    state_close(out32[idx].cpu().numpy(), ref32, 1e-5, "workload 5 periodic fp32")
