@@ -510,6 +510,11 @@ void ctu_fused(CtuArgs<T> P) {
     const bool lev_ok = group_dt(P, g, dt, dh);
     const T hdt = T(0.5 * dt / dh);
     const double dtdh = dt / dh;
+    // The Roe fluxes of this sweep are kept doubled (roe_dir<..., true>: 2F, the
+    // flux sums without their exact factor 1/2); the corrections, the update and
+    // the stored flux planes take that 1/2 instead, with the same values bitwise.
+    const T hdt2 = c.half * hdt;
+    const double hdtdh = 0.5 * dtdh;
     const T *U = P.in + g * GIN;
     T *out = P.out + g * GOUT;
     const int t = threadIdx.x - half * NT;
@@ -615,7 +620,7 @@ void ctu_fused(CtuArgs<T> P) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) zpn[v] = zm[v];
             }
-            if (s >= 0 && in_e1(i, j, s - 1)) n_roe += roe_dir<2>(zpp, zm, c, ftz);
+            if (s >= 0 && in_e1(i, j, s - 1)) n_roe += roe_dir<2, true>(zpp, zm, c, ftz);
         }
         // corrected x and y states of plane kb (whose other two coordinates lie in
         // the interior); the plus states go to LDS for the neighbour's face
@@ -630,10 +635,10 @@ void ctu_fused(CtuArgs<T> P) {
                 if (i >= 0) {  // minus-x state: face i
 #pragma unroll
                     for (int v = 0; v < NV; ++v) p[v] = S.a.xm[v][j + 1][i + 1];
-                    n_pred += !correct_state(p, a, b, hdt, cxm);
+                    n_pred += !correct_state(p, a, b, hdt2, cxm);
                 }
                 if (i < NI) {  // plus-x state: face i + 1
-                    n_pred += !correct_state(xp, a, b, hdt, u);
+                    n_pred += !correct_state(xp, a, b, hdt2, u);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) S.a.cxp[v][j][i + 1] = u[v];
                 }
@@ -644,10 +649,10 @@ void ctu_fused(CtuArgs<T> P) {
                 if (j >= 0) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) p[v] = S.a.ym[v][j + 1][i + 1];
-                    n_pred += !correct_state(p, a, b, hdt, cym);
+                    n_pred += !correct_state(p, a, b, hdt2, cym);
                 }
                 if (j < NI) {
-                    n_pred += !correct_state(yp, a, b, hdt, u);
+                    n_pred += !correct_state(yp, a, b, hdt2, u);
 #pragma unroll
                     for (int v = 0; v < NV; ++v) S.a.cyp[v][j + 1][i] = u[v];
                 }
@@ -689,14 +694,14 @@ void ctu_fused(CtuArgs<T> P) {
             if (in_e1(i + 1, j, s)) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) R[v] = S.a.xm[v][j + 1][i + 2];
-                n_roe += roe_dir<0>(xp, R, c, F);
+                n_roe += roe_dir<0, true>(xp, R, c, F);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) S.a.ftx[v][j + 1][i + 1] = F[v];
             }
             if (in_e1(i, j + 1, s)) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) R[v] = S.a.ym[v][j + 2][i + 1];
-                n_roe += roe_dir<1>(yp, R, c, F);
+                n_roe += roe_dir<1, true>(yp, R, c, F);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) S.a.fty[v][j + 1][i + 1] = F[v];
             }
@@ -706,25 +711,25 @@ void ctu_fused(CtuArgs<T> P) {
             if (in_j && i >= 0) {  // x face i of row j: plus-x of cell i - 1, minus-x of cell i
 #pragma unroll
                 for (int v = 0; v < NV; ++v) L[v] = S.a.cxp[v][j][i];
-                n_roe += roe_dir<0>(L, cxm, c, F);
+                n_roe += roe_dir<0, true>(L, cxm, c, F);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) S.a.fx[v][j][i] = F[v];
                 if (P.flux && (i & 7) == 0) {
                     T *dst = P.flux + g * GFLX + ((0 * 3 + (i >> 3)) * NV) * NINNER + kb * NI + j;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = F[v];
+                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = c.half * F[v];
                 }
             }
             if (in_i && j >= 0) {  // y face j of column i
 #pragma unroll
                 for (int v = 0; v < NV; ++v) L[v] = S.a.cyp[v][j][i];
-                n_roe += roe_dir<1>(L, cym, c, F);
+                n_roe += roe_dir<1, true>(L, cym, c, F);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) S.a.fy[v][j][i] = F[v];
                 if (P.flux && (j & 7) == 0) {
                     T *dst = P.flux + g * GFLX + ((1 * 3 + (j >> 3)) * NV) * NINNER + kb * NI + i;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = F[v];
+                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = c.half * F[v];
                 }
             }
         }
@@ -739,13 +744,13 @@ void ctu_fused(CtuArgs<T> P) {
                 a[v] = S.a.ftx[v][j + 1][i + 1] - S.a.ftx[v][j + 1][i];
                 b[v] = S.a.fty[v][j + 1][i + 1] - S.a.fty[v][j][i + 1];
             }
-            if (s >= 0) n_pred += !correct_state(zm, a, b, hdt, czm);
+            if (s >= 0) n_pred += !correct_state(zm, a, b, hdt2, czm);
             if (s >= 0) {  // final z flux at face s: plus-z of plane s - 1, minus-z of plane s
-                n_roe += roe_dir<2>(czp, czm, c, fz);
+                n_roe += roe_dir<2, true>(czp, czm, c, fz);
                 if (P.flux && (s & 7) == 0) {
                     T *dst = P.flux + g * GFLX + ((2 * 3 + (s >> 3)) * NV) * NINNER + j * NI + i;
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = fz[v];
+                    for (int v = 0; v < NV; ++v) dst[v * NINNER] = c.half * fz[v];
                 }
             }
             if (kb >= 0) {
@@ -757,7 +762,7 @@ void ctu_fused(CtuArgs<T> P) {
                                        (double(S.a.fy[v][j + 1][i]) - double(S.a.fy[v][j][i]));
                     const double dfz = double(fz[v]) - double(fzb[v]);
                     const double u0 = double(U[v * (NP * NP * NP) + ((kb + NG) * NP + jj) * NP + ii]);
-                    const T o = T(u0 - dtdh * (dxy + dfz));
+                    const T o = T(u0 - hdtdh * (dxy + dfz));
                     out[v * (NI * NI * NI) + (kb * NI + j) * NI + i] = o;
                     un[v] = o;
                     st[v] += double(o);
@@ -766,7 +771,7 @@ void ctu_fused(CtuArgs<T> P) {
                 n_bad += sp_ != sp_;
                 st[5] = max_nan(st[5], sp_);
             }
-            if (s < NI) n_pred += !correct_state(zpn, a, b, hdt, czp);
+            if (s < NI) n_pred += !correct_state(zpn, a, b, hdt2, czp);
 #pragma unroll
             for (int v = 0; v < NV; ++v) fzb[v] = fz[v];
         }
