@@ -719,7 +719,8 @@ def counter_pass(args, dev):
     dt_dev = torch.empty(1, dtype=torch.float64, device=dev)
     hydro.group_stats(st, GAMMA, out=stats)
     hydro.step_reduce(stats, None, dh_dev, CFL, dt_out=dt_dev)
-    pad_state = st if args.counter_kernel == "rtvd" else None  # the relaxing TVD reads the grid in place
+    # the relaxing TVD and the fused periodic step read the grid in place
+    pad_state = st if args.counter_kernel in ("rtvd", "periodic") else None
     del st
     out = torch.empty((g ** 3, 5, 16, 16, 16), dtype=pad.dtype, device=dev)
     v = args.variant or 0
@@ -727,6 +728,10 @@ def counter_pass(args, dev):
         if args.counter_kernel == "solve":
             hydro.hydro_solve_batched(pad, None, dt_dev, dh_dev, GAMMA, out=out, group_stats=stats, variant=v,
                                       grid=args.grid)
+        elif args.counter_kernel == "periodic":
+            hydro.hydro_solve_periodic(pad_state if k % 2 == 0 else out, g, g, g, dt_dev, dh_dev, GAMMA,
+                                       out=out if k % 2 == 0 else pad_state, group_stats=stats, variant=v,
+                                       grid=args.grid)
         elif args.counter_kernel == "ctu":
             hydro.ctu_solve_batched(pad, None, dt_dev, dh_dev, GAMMA, out=out, group_stats=stats,
                                     variant=hydro.CTU_FUSED)
@@ -760,9 +765,9 @@ def main():
                          "every dispatch, and the device generator issues thousands), copy it over, run a "
                          "plain 1 GiB device copy, then N batched solves of --dtype at --variant/--grid, "
                          "and exit without timing")
-    ap.add_argument("--counter-kernel", choices=["solve", "ctu", "rtvd"], default="solve",
-                    help="with --counter-pass: the batched solver (default), the fused CTU step or the "
-                         "relaxing-TVD step (alternating sweep orders)")
+    ap.add_argument("--counter-kernel", choices=["solve", "periodic", "ctu", "rtvd"], default="solve",
+                    help="with --counter-pass: the batched solver (default), the fused periodic step, the "
+                         "fused CTU step or the relaxing-TVD step (alternating sweep orders)")
     ap.add_argument("--variant", type=int, default=None,
                     help="use this compiled solver variant (with --grid) instead of tuning")
     ap.add_argument("--grid", type=int, default=0, help="launch grid with --variant (0: one per group)")

@@ -79,8 +79,9 @@ typedef struct gamer_opts {
      * agree to about 1e-13 and FP32 results to about 1e-6 relative (the
      * compiler may contract multiply-adds differently). */
     int32_t variant;
-    /* Work-groups launched: 0 launches one per group; g > 0 launches
-     * min(g, n_groups) persistent work-groups that stride over the groups. */
+    /* Work-groups launched: 0 launches one per group (periodic entry points:
+     * one per z segment, see zseg); g > 0 launches at most g persistent
+     * work-groups that stride over the groups (segments). */
     int32_t grid;
     /* Variables the slopes are limited in: GAMER_LIMIT_PRIMITIVE (0, the
      * default) limits each primitive variable; GAMER_LIMIT_CHARACTERISTIC (1)
@@ -88,7 +89,15 @@ typedef struct gamer_opts {
      * along each direction (the paper does not say which; both are common
      * choices of the MUSCL-Hancock reconstruction step, Toro 2009, Sec. 14). */
     int32_t limiting;
-    int32_t reserved; /* must be 0 */
+    /* Periodic entry points (gamer_hydro_solve_periodic*): the groups of one
+     * (x, y) column of the grid are taken zseg at a time along z, and one
+     * work-group sweeps such a segment as one run of planes, so the planes and z
+     * faces that neighbouring groups of the segment share are computed once and
+     * read once.  Results, flux planes and stats (fallback counts included) are
+     * the same for every zseg.  0 lets the library choose (the largest divisor
+     * of gz that leaves at least 12,288 segments, else 1); values above gz act
+     * as gz.  Must be 0 for the other entry points. */
+    int32_t zseg;
     /* Two device counters the step adds to, or NULL (8-byte aligned device
      * memory, zeroed by the caller; accumulated with atomics, so their order of
      * arrival is free but the totals are exact):

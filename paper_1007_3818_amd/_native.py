@@ -28,7 +28,7 @@ LIMIT_CHARACTERISTIC = 1
 
 class GamerOpts(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("variant", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("limiting", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("limiting", ctypes.c_int32), ("zseg", ctypes.c_int32),
                 ("bad_count_dev", ctypes.c_void_p)]
 
 

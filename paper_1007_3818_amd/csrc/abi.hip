@@ -96,10 +96,23 @@ int noalloc_scratch(void **out) {
     return GAMER_OK;
 }
 
+// Groups per z segment of a periodic grid when the caller leaves it to the
+// library: the largest divisor of gz that still leaves at least 12,288
+// segments (sixteen per slot of a full chip: 256 CUs x 3 work-groups), so that
+// the last round of work-groups is a small part of the launch; 1 on grids too
+// small for that.
+int auto_zseg(int gx, int gy, int gz) {
+    const int64_t cols = int64_t(gx) * gy;
+    int best = 1;
+    for (int d = 2; d <= gz; ++d)
+        if (gz % d == 0 && cols * (gz / d) >= 12288) best = d;
+    return best;
+}
+
 // Tunables shared by the solver entry points; returns GAMER_OK or an error.
 template <typename T>
 int parse_opts(const gamer_opts *opts, double *theta, int *variant, int64_t *grid, int *limiting,
-               unsigned long long **bad) {
+               unsigned long long **bad, int *zseg = nullptr) {
     *theta = (opts && opts->theta != 0.0) ? opts->theta : 1.5;
     if (!(*theta >= 1.0 && *theta <= 2.0)) return fail(GAMER_EINVAL, "theta must lie in [1, 2]");
     *variant = opts ? opts->variant : 0;
@@ -110,7 +123,13 @@ int parse_opts(const gamer_opts *opts, double *theta, int *variant, int64_t *gri
     if (*grid < 0) return fail(GAMER_EINVAL, "grid must be >= 0");
     if (*limiting != GAMER_LIMIT_PRIMITIVE && *limiting != GAMER_LIMIT_CHARACTERISTIC)
         return fail(GAMER_EINVAL, "limiting must be GAMER_LIMIT_PRIMITIVE or GAMER_LIMIT_CHARACTERISTIC");
-    if (opts && opts->reserved != 0) return fail(GAMER_EINVAL, "gamer_opts.reserved must be 0");
+    const int zs = opts ? opts->zseg : 0;
+    if (zseg) {
+        if (zs < 0) return fail(GAMER_EINVAL, "gamer_opts.zseg must be >= 0");
+        *zseg = zs;
+    } else if (zs != 0) {
+        return fail(GAMER_EINVAL, "gamer_opts.zseg applies to the periodic entry points only (must be 0)");
+    }
     *bad = opts ? reinterpret_cast<unsigned long long *>(opts->bad_count_dev) : nullptr;
     if (reinterpret_cast<uintptr_t>(*bad) % 8)
         return fail(GAMER_EINVAL, "gamer_opts.bad_count_dev must be 8-byte aligned");
@@ -153,6 +172,7 @@ int solve_common(const S *in, int64_t n, const int8_t *level, const double *dt_d
     p.n_groups = n;
     p.n_levels = dt_dev ? n_levels : 1;
     p.char_limiting = limiting;
+    p.zseg = 1;
     p.bad = bad;
     return check_hip(launch_solve<S, T>(p, variant, grid, stream), "solver launch");
 }
@@ -172,10 +192,10 @@ int periodic_common(const S *state, int gx, int gy, int gz, const double *dt_dev
         return fail(GAMER_EINVAL, "state and state_out must be different arrays");
     if (!(isfinite(gamma) && gamma > 1.0)) return fail(GAMER_EINVAL, "gamma must be > 1");
     double theta;
-    int variant, limiting;
+    int variant, limiting, zseg;
     int64_t grid;
     unsigned long long *bad;
-    if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting, &bad)) return e;
+    if (const int e = parse_opts<T>(opts, &theta, &variant, &grid, &limiting, &bad, &zseg)) return e;
     SolveParams<S> p;
     p.in = state;
     p.gx = gx;
@@ -193,6 +213,7 @@ int periodic_common(const S *state, int gx, int gy, int gz, const double *dt_dev
     p.n_groups = n;
     p.n_levels = 1;
     p.char_limiting = limiting;
+    p.zseg = zseg == 0 ? auto_zseg(gx, gy, gz) : (zseg < gz ? zseg : gz);
     p.bad = bad;
     return check_hip(launch_solve<S, T>(p, variant, grid, g_stream), "solver launch");
 }

@@ -315,38 +315,45 @@ __device__ __forceinline__ bool roe_dir(const T UL[NV], const T UR[NV], const Co
 // (thread index t, 0 .. NTHREADS - 1, NTHREADS a multiple of 64 when the
 // work-group holds several such sets): stats 0..4 and 6..7 are summed, stat 5
 // is a maximum that keeps NaN.  Thread 0 writes the result to dst (if not
-// null).  `red` must hold NTHREADS * NSTAT doubles of LDS.
-template <int NTHREADS>
+// null).  The values go through LDS PART at a time; `red` must hold
+// NTHREADS * PART doubles.  Each value is folded in the same order whatever
+// PART is: thread t takes the values of threads t, t + 64, ..., then the 64
+// partial results are folded by halving.
+template <int NTHREADS, int PART = NSTAT>
 __device__ __forceinline__ void block_reduce_stats(double st[NSTAT], double *red, double *dst,
                                                    int t = threadIdx.x) {
+    static_assert(NSTAT % PART == 0, "whole passes");
 #pragma unroll
-    for (int q = 0; q < NSTAT; ++q) red[q * NTHREADS + t] = st[q];
-    __syncthreads();
-    if (t < 64) {
-        double acc[NSTAT];
+    for (int q0 = 0; q0 < NSTAT; q0 += PART) {
 #pragma unroll
-        for (int q = 0; q < NSTAT; ++q) {
-            double a = red[q * NTHREADS + t];
-            for (int s = t + 64; s < NTHREADS; s += 64) {
-                const double b = red[q * NTHREADS + s];
-                a = (q == 5) ? max_nan(a, b) : a + b;
+        for (int q = 0; q < PART; ++q) red[q * NTHREADS + t] = st[q0 + q];
+        __syncthreads();
+        if (t < 64) {
+            double acc[PART];
+#pragma unroll
+            for (int q = 0; q < PART; ++q) {
+                double a = red[q * NTHREADS + t];
+                for (int s = t + 64; s < NTHREADS; s += 64) {
+                    const double b = red[q * NTHREADS + s];
+                    a = (q0 + q == 5) ? max_nan(a, b) : a + b;
+                }
+                acc[q] = a;
             }
-            acc[q] = a;
-        }
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
+            for (int off = 32; off >= 1; off >>= 1) {
 #pragma unroll
-            for (int q = 0; q < NSTAT; ++q) {
-                const double b = __shfl_down(acc[q], off, 64);
-                acc[q] = (q == 5) ? max_nan(acc[q], b) : acc[q] + b;
+                for (int q = 0; q < PART; ++q) {
+                    const double b = __shfl_down(acc[q], off, 64);
+                    acc[q] = (q0 + q == 5) ? max_nan(acc[q], b) : acc[q] + b;
+                }
+            }
+            if (t == 0 && dst) {
+#pragma unroll
+                for (int q = 0; q < PART; ++q) dst[q0 + q] = acc[q];
             }
         }
-        if (t == 0 && dst) {
-#pragma unroll
-            for (int q = 0; q < NSTAT; ++q) dst[q] = acc[q];
-        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 }  // namespace

@@ -40,6 +40,8 @@ struct SolveParams {
     int64_t n_groups;
     int n_levels;       // entries of dt_dev and dh_dev
     int char_limiting;  // 0: limit primitive variables, 1: characteristic variables
+    int zseg;           // periodic input: groups per z segment of a column that one
+                        // work-group sweeps in one pass (>= 1)
     // device counters or nullptr: [0] output cells that are not physical or not
     // finite, [1] groups whose level byte lies outside [0, n_levels)
     unsigned long long *bad;

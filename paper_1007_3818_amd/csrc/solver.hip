@@ -113,6 +113,18 @@ __device__ __forceinline__ void ring_cell(int r, int &ci, int &cj) {
     }
 }
 
+// Stats values reduced per pass when a group's stats go out in the middle of a
+// unit: the pass's values for every thread must fit in the flux arrays and the
+// face-16 states (sx, sy, rf), the LDS free at that point.
+template <typename T>
+constexpr int FLUSH_PART = sizeof(T) == 4 ? 4 : 8;
+template <typename T>
+constexpr size_t FLUX_LDS = sizeof(Lds<T>::sx) + sizeof(Lds<T>::sy) + sizeof(Lds<T>::rf);
+static_assert(320 * FLUSH_PART<float> * sizeof(double) <= FLUX_LDS<float> &&
+                  320 * FLUSH_PART<double> * sizeof(double) <= FLUX_LDS<double> &&
+                  NSTAT % FLUSH_PART<float> == 0 && NSTAT % FLUSH_PART<double> == 0,
+              "a stats pass must fit in the flux arrays");
+
 // One work-group of NT threads advances one group at a time (grid-stride).
 //  NT = 320: threads 0..255 own the interior columns, 256..319 the ghost-layer
 //            cells of every plane (5 waves).
@@ -134,8 +146,24 @@ void solve_kernel(SolveParams<S_> P) {
 
     const Consts<T> c = make_consts<T>(P.gamma, P.theta);
 
-    for (int64_t slot = blockIdx.x; slot < P.n_groups; slot += gridDim.x) {
-        const int64_t g = xcd_group(slot, P.n_groups);
+    // A unit is one group of padded input, or, for periodic input, a run of
+    // nseg groups along z of one (x, y) column, swept as one sequence of planes
+    // (units numbered column fastest, then z segment).
+    const int64_t cols = PERIODIC ? int64_t(P.gx) * P.gy : 1;
+    const int64_t n_units = PERIODIC ? cols * ((P.gz + P.zseg - 1) / P.zseg) : P.n_groups;
+    for (int64_t slot = blockIdx.x; slot < n_units; slot += gridDim.x) {
+        const int64_t unit = xcd_group(slot, n_units);
+        int bx = 0, by = 0, bz = 0, nseg = 1;
+        int64_t g = unit;  // the unit's first group; group q of the unit is g + q * cols
+        if (PERIODIC) {
+            const int64_t col = unit % cols;
+            bx = int(col % P.gx);
+            by = int(col / P.gx);
+            bz = int(unit / cols) * P.zseg;
+            nseg = P.gz - bz < P.zseg ? P.gz - bz : P.zseg;
+            g = col + cols * bz;
+        }
+        const int nplanes = NI * nseg;  // interior planes 0 .. nplanes-1 of the unit
         double dt = P.dt, dh = P.dh;
         if (P.dt_dev && !level_dt(P.level, g, P.n_levels, P.dt_dev, P.dh_dev, dt, dh)) {
             // a level byte out of range: the group runs on NaN dt and dh (its
@@ -145,18 +173,13 @@ void solve_kernel(SolveParams<S_> P) {
         const double dtdh = dt / dh;
         const double hdtdh = 0.5 * dtdh;  // the Roe fluxes below are kept doubled (2F)
 
-        // ---- where padded cell (ip, jp, kp) of this group lives in the input ----
+        // ---- where padded cell (ip, jp, kp) of this unit lives in the input ----
         // Padded input: the group's own padded block.  Periodic input: the cell at
         // the wrapped global position, in whichever group holds it; an offset is
         // (group index) * 20480 + (cell within the group), the group index split
-        // into an x/y part and a z part.
+        // into an x/y part and a z part.  kp counts planes from the unit's first
+        // group, so it runs past 19 when the unit holds several groups.
         constexpr int VSTRIDE = PERIODIC ? NI * NI * NI : NP * NP * NP;
-        int bx = 0, by = 0, bz = 0;
-        if (PERIODIC) {
-            bx = int(g % P.gx);
-            by = int((g / P.gx) % P.gy);
-            bz = int(g / (int64_t(P.gx) * P.gy));
-        }
         // x/y part: (group index part, cell part)
         auto xy_part = [&](int ip, int jp, int &gpart) -> int {
             if (!PERIODIC) {
@@ -263,8 +286,18 @@ void solve_kernel(SolveParams<S_> P) {
         T zp[NV];            // +z state of this column at the previous plane
         T fz[NV];            // z flux below the current plane
         double st[6];        // sums of the 5 conserved variables, max signal speed
-        int n_pred = 0, n_roe = 0;  // fallback counts
+        int n_pred = 0, n_roe = 0;  // fallback counts of the group being finished
         unsigned n_bad = 0;  // output cells that are not physical or not finite
+        // With several groups per unit, a plane next to a group boundary serves
+        // two groups: plane 16q is group q's plane 0 and group q-1's ghost plane
+        // 16, plane 16q-1 also group q's ghost plane -1, and the z face between
+        // them is face 16 of one and face 0 of the other.  Each group's counts
+        // take such a plane's interior predictions and z face as its own padded
+        // step would, so they equal a one-group sweep's.  `step` holds this
+        // step's fallbacks (bit 0 interior cell, bit 1 ghost-layer cell, bit 2 z
+        // face, bits 3.. number of x and y faces), `carry` the next group's
+        // counts so far (predictions + 65536 * faces).
+        int step = 0, carry = 0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) st[q] = 0.0;
 #pragma unroll
@@ -278,12 +311,17 @@ void solve_kernel(SolveParams<S_> P) {
         // longer reads by then.  Consuming it there, before the update's stores
         // are issued, keeps the wait for the loads from also waiting out those
         // stores (memory operations complete in issue order).
-        for (int k = -1; k <= NI; ++k) {
-            const bool ahead = k + 2 <= NI + 1;
+        for (int k = -1; k <= nplanes; ++k) {
+            // plane k of the unit is plane kl of its group gk (k in 0 .. nplanes-1;
+            // with padded input, the group itself and k)
+            const int kq = PERIODIC ? k >> 4 : 0, kl = PERIODIC ? k & 15 : k;
+            const int64_t gk = PERIODIC ? g + int64_t(kq) * cols : g;
+            const bool ahead = k + 2 <= nplanes + 1;
             if (ahead) fetch(k + 2);
             __syncthreads();  // B1: plane k+1 visible; planes k-1, k, k+1 in the ring
 
-            const bool edge = (k < 0 || k >= NI);
+            const bool edge = (k < 0 || k >= nplanes);
+            if constexpr (PERIODIC) step = 0;
             // ghost-layer cell of this thread in this plane (-1: none)
             const int ring = edge ? -1 : (SPLIT ? my_ring : (wave == (k & 3) ? my_ring : -1));
 
@@ -348,7 +386,10 @@ void solve_kernel(SolveParams<S_> P) {
                 T Ub[3][2][NV];
                 if (!predict(W0, dW, T(0.5 * dtdh), c, Ub)) {
                     // first-order fallback: every face of the cell takes the cell average
-                    ++n_pred;
+                    if constexpr (PERIODIC)
+                        step |= round == 0 ? 1 : 2;
+                    else
+                        ++n_pred;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         const T u0 = T(cell_ptr(ci + NG, cj + NG, k + NG)[v * VSTRIDE]);
@@ -401,11 +442,31 @@ void solve_kernel(SolveParams<S_> P) {
             T fzn[NV];
             auto solve_z = [&]() {
                 if (inner && k >= 0) {
-                    n_roe += roe_dir<2, true>(zp, zm, c, fzn);
-                    if (P.flux && (k & 7) == 0) {
-                        S_ *dst = P.flux + g * GFLX + ((2 * 3 + (k >> 3)) * NV) * NINNER + jj * NI + ii;
+                    const bool fb = roe_dir<2, true>(zp, zm, c, fzn);
+                    if constexpr (PERIODIC)
+                        step |= int(fb) << 2;
+                    else
+                        n_roe += fb;
+                    if (P.flux) {
+                        const int off = jj * NI + ii;
+                        if constexpr (PERIODIC) {
+                            // face kl of group gk (below the unit's last plane), and face 16
+                            // of the group below when the face lies on a group boundary
+                            if (k < nplanes && (kl & 7) == 0) {
+                                S_ *dst = P.flux + gk * GFLX + ((2 * 3 + (kl >> 3)) * NV) * NINNER + off;
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(c.half * fzn[v]);
+                                for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(c.half * fzn[v]);
+                            }
+                            if (kl == 0 && k > 0) {
+                                S_ *dst = P.flux + (gk - cols) * GFLX + ((2 * 3 + 2) * NV) * NINNER + off;
+#pragma unroll
+                                for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(c.half * fzn[v]);
+                            }
+                        } else if ((k & 7) == 0) {
+                            S_ *dst = P.flux + g * GFLX + ((2 * 3 + (k >> 3)) * NV) * NINNER + off;
+#pragma unroll
+                            for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(c.half * fzn[v]);
+                        }
                     }
                 }
             };
@@ -439,11 +500,15 @@ void solve_kernel(SolveParams<S_> P) {
                         UL[v] = S.sx[v][row][f];
                         UR[v] = round == 0 ? xm[v] : S.rf[0][v][row];
                     }
-                    n_roe += roe_dir<0, true>(UL, UR, c, F);
+                    const bool fb = roe_dir<0, true>(UL, UR, c, F);
+                    if constexpr (PERIODIC)
+                        step += int(fb) << 3;
+                    else
+                        n_roe += fb;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) S.sx[v][row][f] = F[v];
                     if (P.flux && (f & 7) == 0) {
-                        S_ *dst = P.flux + g * GFLX + ((0 * 3 + (f >> 3)) * NV) * NINNER + k * NI + row;
+                        S_ *dst = P.flux + gk * GFLX + ((0 * 3 + (f >> 3)) * NV) * NINNER + kl * NI + row;
 #pragma unroll
                         for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(c.half * F[v]);
                     }
@@ -467,11 +532,15 @@ void solve_kernel(SolveParams<S_> P) {
                         UL[v] = S.sy[v][f][col];
                         UR[v] = round == 0 ? ym[v] : S.rf[1][v][col];
                     }
-                    n_roe += roe_dir<1, true>(UL, UR, c, F);
+                    const bool fb = roe_dir<1, true>(UL, UR, c, F);
+                    if constexpr (PERIODIC)
+                        step += int(fb) << 3;
+                    else
+                        n_roe += fb;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) S.sy[v][f][col] = F[v];
                     if (P.flux && (f & 7) == 0) {
-                        S_ *dst = P.flux + g * GFLX + ((1 * 3 + (f >> 3)) * NV) * NINNER + k * NI + col;
+                        S_ *dst = P.flux + gk * GFLX + ((1 * 3 + (f >> 3)) * NV) * NINNER + kl * NI + col;
 #pragma unroll
                         for (int v = 0; v < NV; ++v) dst[v * NINNER] = S_(c.half * F[v]);
                     }
@@ -485,9 +554,12 @@ void solve_kernel(SolveParams<S_> P) {
             // are issued before the barrier, so their latency overlaps the wait.
             constexpr bool EARLY = sizeof(T) == 4;
             S_ uold[NV];
+            // plane k-1 of the unit: plane ul of group gu
+            const int ul = PERIODIC ? (k - 1) & 15 : k - 1;
+            const int64_t gu = PERIODIC ? g + int64_t((k - 1) >> 4) * cols : g;
             auto load_old = [&]() {
                 // an interior cell: in the group's own block in both input kinds
-                const S_ *src = PERIODIC ? P.in + g * GOUT + (k - 1) * NINNER
+                const S_ *src = PERIODIC ? P.in + gu * GOUT + ul * NINNER
                                          : P.in + g * GIN + (k - 1 + NG) * NPL + NG * NP + NG;
                 const unsigned off = PERIODIC ? unsigned(t) : unsigned(jj * NP + ii);
 #pragma unroll
@@ -500,8 +572,7 @@ void solve_kernel(SolveParams<S_> P) {
             if (inner) {
                 if (k >= 1) {
                     // plane k-1 is complete: U - dt/dh ((dF_x + dF_y) + dF_z)
-                    const int kk = k - 1;
-                    S_ *dst = P.out + g * GOUT + kk * NINNER;
+                    S_ *dst = P.out + gu * GOUT + ul * NINNER;
                     if (!EARLY) load_old();
                     T un[NV];
 #pragma unroll
@@ -530,6 +601,43 @@ void solve_kernel(SolveParams<S_> P) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) zp[v] = zpn[v];
             }
+
+            if constexpr (PERIODIC) {
+                // this step's fallbacks to the groups they belong to (see `step`)
+                const int pi = step & 1, pr = (step >> 1) & 1, rz = (step >> 2) & 1, rxy = step >> 3;
+                if (k < 0) {
+                    n_pred += pi;  // the first group's ghost plane -1
+                } else if (k == nplanes) {
+                    n_pred += pi;  // the last group's ghost plane 16 and face 16
+                    n_roe += rz;
+                } else if (kl == 0 && k > 0) {
+                    n_pred += pi;  // group kq - 1: ghost plane 16, face 16
+                    n_roe += rz;
+                    carry += (pi + pr) + ((rz + rxy) << 16);  // group kq: plane 0, face 0
+                } else {
+                    n_pred += pi + pr;
+                    n_roe += rz + rxy;
+                    if (kl == 15 && k < nplanes - 1) carry += pi;  // group kq + 1's ghost plane -1
+                }
+                // Group kq - 1 is complete at a boundary inside the unit: its stats
+                // go out now (the unit's last group after the sweep).  The flux
+                // arrays are free until the next step's predictions; they hold the
+                // reduction's values once every thread has read this step's fluxes.
+                if (kl == 0 && k > 0 && k < nplanes) {
+                    if (P.stats) {
+                        __syncthreads();
+                        double all[NSTAT] = {st[0], st[1], st[2], st[3], st[4], st[5], double(n_pred),
+                                             double(n_roe)};
+                        block_reduce_stats<NT, FLUSH_PART<T>>(all, reinterpret_cast<double *>(&S.sx[0][0][0]),
+                                                              P.stats + (gk - cols) * NSTAT);
+                    }
+                    n_pred = carry & 0xffff;
+                    n_roe = carry >> 16;
+                    carry = 0;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) st[q] = 0.0;
+                }
+            }
         }
 
         if (P.bad && n_bad) atomicAdd(P.bad, (unsigned long long)n_bad);
@@ -538,7 +646,7 @@ void solve_kernel(SolveParams<S_> P) {
                                  double(n_roe)};
             // S.w is free now (B3 of the last step passed); reuse it for the reduction
             block_reduce_stats<NT>(all, reinterpret_cast<double *>(&S.w[0][0][0]),
-                                   P.stats + g * NSTAT);
+                                   P.stats + (g + int64_t(nseg - 1) * cols) * NSTAT);
         } else {
             __syncthreads();
         }
@@ -589,8 +697,14 @@ void launch_variant(const SolveParams<S_> &p, dim3 blocks, hipStream_t s) {
 template <typename S_, typename T>
 hipError_t launch_solve(const SolveParams<S_> &p, int variant, int64_t grid, hipStream_t s) {
     if (p.n_groups <= 0) return hipSuccess;
+    // work units: groups, or z segments of the columns of a periodic grid
+    int64_t units = p.n_groups;
+    if (p.gx > 0) {
+        if (p.zseg < 1 || p.zseg > p.gz) return hipErrorInvalidValue;
+        units = int64_t(p.gx) * p.gy * ((p.gz + p.zseg - 1) / p.zseg);
+    }
     const int64_t max_grid = int64_t(1) << 30;
-    int64_t g = grid > 0 ? (grid < p.n_groups ? grid : p.n_groups) : p.n_groups;
+    int64_t g = grid > 0 ? (grid < units ? grid : units) : units;
     if (g > max_grid) g = max_grid;
     const dim3 blocks = dim3(unsigned(g));
     switch (variant < 0 ? 0 : variant) {

@@ -57,11 +57,12 @@ def _bad_counter(bad_count):
     return bad_count.data_ptr()
 
 
-def _opts(theta, variant, grid, limiting, bad_count=None):
-    if theta is None and variant is None and grid is None and limiting is None and bad_count is None:
+def _opts(theta, variant, grid, limiting, bad_count=None, zseg=None):
+    if (theta is None and variant is None and grid is None and limiting is None and bad_count is None
+            and zseg is None):
         return None
     lim = {None: 0, "primitive": 0, "characteristic": 1}.get(limiting, limiting)
-    return _native.GamerOpts(float(theta or 0.0), int(variant or 0), int(grid or 0), int(lim), 0,
+    return _native.GamerOpts(float(theta or 0.0), int(variant or 0), int(grid or 0), int(lim), int(zseg or 0),
                              _bad_counter(bad_count))
 
 
@@ -135,10 +136,12 @@ def hydro_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxe
 
 def hydro_solve_periodic(state, gx, gy, gz, dt_dev, dh_dev, gamma, out=None, fluxes_out=None,
                          group_stats=None, theta=None, variant=None, grid=None, limiting=None,
-                         compute=None, bad_count=None):
+                         compute=None, bad_count=None, zseg=None):
     """One step of a uniform periodic grid; ghost cells are read from the
     neighbouring groups in place (no padded copy).  `out` must not be `state`.
-    Options as in hydro_solve_batched."""
+    zseg: groups of a column swept together by one work-group (None or 0: the
+    library's choice); the results do not depend on it.  Other options as in
+    hydro_solve_batched."""
     fn = _solver_fn("gamer_hydro_solve_periodic", state.dtype, compute)
     _need(state, (NV, NI, NI, NI), state.dtype, "state")
     n = state.shape[0]
@@ -154,7 +157,7 @@ def hydro_solve_periodic(state, gx, gy, gz, dt_dev, dh_dev, gamma, out=None, flu
     for t, nm in ((dt_dev, "dt_dev"), (dh_dev, "dh_dev")):
         if t.dtype != torch.float64 or not t.is_cuda or t.numel() < 1:
             raise ValueError(f"{nm} must be a GPU float64 tensor")
-    opts = _opts(theta, variant, grid, limiting, bad_count)
+    opts = _opts(theta, variant, grid, limiting, bad_count, zseg)
     _stream()
     _native.check(fn(_ptr(state), int(gx), int(gy), int(gz), _ptr(dt_dev), _ptr(dh_dev), float(gamma),
                      _ptr(fluxes_out), _ptr(out), _ptr(group_stats),

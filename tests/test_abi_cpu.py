@@ -37,11 +37,11 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_opts_struct_layout():
-    # gamer_opts: double theta, int32 variant, int32 grid, int32 limiting, int32 reserved,
+    # gamer_opts: double theta, int32 variant, int32 grid, int32 limiting, int32 zseg,
     # uint64_t *bad_count_dev
     assert ctypes.sizeof(_native.GamerOpts) == 32
     assert _native.GamerOpts.variant.offset == 8 and _native.GamerOpts.grid.offset == 12
-    assert _native.GamerOpts.limiting.offset == 16 and _native.GamerOpts.reserved.offset == 20
+    assert _native.GamerOpts.limiting.offset == 16 and _native.GamerOpts.zseg.offset == 20
     assert _native.GamerOpts.bad_count_dev.offset == 24
 
 
@@ -52,13 +52,13 @@ def test_opts_struct_layout_matches_header(tmp_path):
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gamer_hydro.h"\n'
                    'int main(void) { printf("%zu %zu %zu %zu %zu %zu", sizeof(gamer_opts),'
                    ' offsetof(gamer_opts, variant), offsetof(gamer_opts, grid),'
-                   ' offsetof(gamer_opts, limiting), offsetof(gamer_opts, reserved),'
+                   ' offsetof(gamer_opts, limiting), offsetof(gamer_opts, zseg),'
                    ' offsetof(gamer_opts, bad_count_dev)); return 0; }\n')
     exe = tmp_path / "o"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     O = _native.GamerOpts
-    assert got == [ctypes.sizeof(O), O.variant.offset, O.grid.offset, O.limiting.offset, O.reserved.offset,
+    assert got == [ctypes.sizeof(O), O.variant.offset, O.grid.offset, O.limiting.offset, O.zseg.offset,
                    O.bad_count_dev.offset]
 
 
@@ -128,12 +128,18 @@ def test_batched_argument_errors(lib):
 def test_limiting_and_mixed_argument_errors(lib):
     E = _native.GAMER_EINVAL
     Q = ctypes.c_void_p(0x2000)
-    for lim, res in ((2, 0), (-1, 0), (0, 3)):
-        bad = _native.GamerOpts(1.5, 0, 0, lim, res)
+    # a bad limiting value or a negative z-segment length: every solver entry point
+    for lim, zseg in ((2, 0), (-1, 0), (0, -1)):
+        bad = _native.GamerOpts(1.5, 0, 0, lim, zseg)
         assert lib.gamer_hydro_solve_batched(P, 4, None, P, P, 1, 1.4, None, Q, None,
                                              ctypes.byref(bad), None) == E
         assert lib.gamer_hydro_solve_periodic_mixed(P, 2, 2, 2, P, P, 1.4, None, Q, None,
                                                     ctypes.byref(bad)) == E
+    # a z-segment length is for the periodic entry points only
+    bad = _native.GamerOpts(1.5, 0, 0, 0, 3)
+    assert lib.gamer_hydro_solve_batched(P, 4, None, P, P, 1, 1.4, None, Q, None, ctypes.byref(bad), None) == E
+    assert b"zseg" in lib.gamer_last_error()
+    assert lib.gamer_ctu_solve_batched(P, 4, None, P, P, 1, 1.4, None, Q, None, ctypes.byref(bad), None, 0) == E
     f = lib.gamer_hydro_solve_batched_mixed
     assert f(P, 4, None, None, P, 1, 1.4, None, Q, None, None, None) == E  # no dt_dev
     assert f(P, 4, None, P, None, 1, 1.4, None, Q, None, None, None) == E  # no dh_dev

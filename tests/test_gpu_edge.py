@@ -38,7 +38,7 @@ def test_zero_groups_every_entry_point(gpu):
     dt_dev = torch.tensor([1e-3], dtype=torch.float64, device=gpu)
     dh_dev = torch.tensor([1e-2], dtype=torch.float64, device=gpu)
     work = torch.full((1024,), 3, dtype=torch.uint8, device=gpu)
-    opts = [_native.GamerOpts(theta=1.5, variant=v, grid=0, limiting=0, reserved=0, bad_count_dev=None)
+    opts = [_native.GamerOpts(theta=1.5, variant=v, grid=0, limiting=0, zseg=0, bad_count_dev=None)
             for v in (0, 1)]
     P, D, F, S = _p, _p(d), _p(f), _p(st)
     calls = {

@@ -2,8 +2,9 @@
 through the C ABI.
 
 Bar against the ghost-fill kernel followed by the batched step with the same
-variant (state, fluxes, per-group stats), for every compiled variant and
-several launch grids: FP64 bitwise; FP32 within 1e-6 relative (the periodic
+variant (state, fluxes, per-group stats), for every compiled variant, several
+launch grids and several z-segment lengths (one work-group sweeping 1, 2, 3 or
+all the groups of a column as one run of planes): FP64 bitwise; FP32 within 1e-6 relative (the periodic
 kernel is its own instantiation, and the compiler may contract a float
 multiply-add into an FMA in one and not in the other), fallback counts exact.
 Against the oracle's own ghost fill + step: FP64 1e-12 per cell, relative to
@@ -51,13 +52,14 @@ def test_fused_equals_pack_then_solve(gpu, dtype):
             s_a = torch.empty((n, 8), dtype=torch.float64, device=gpu)
             a = hydro.hydro_solve_batched(pad, None, dt_dev, dh_dev, G53, fluxes_out=fl_a,
                                           group_stats=s_a, variant=v)
-            for grid in (0, 7, 256):
+            for grid, zseg in ((0, None), (7, None), (256, None), (0, 2), (7, 3), (0, gz), (5, gz)):
+                # zseg: groups of a column swept as one run of planes by one work-group
                 fl_b = torch.full_like(fl_a, float("nan"))
                 s_b = torch.full_like(s_a, float("nan"))
                 b = hydro.hydro_solve_periodic(st, gx, gy, gz, dt_dev, dh_dev, G53, fluxes_out=fl_b,
-                                               group_stats=s_b, variant=v, grid=grid)
+                                               group_stats=s_b, variant=v, grid=grid, zseg=zseg)
                 torch.cuda.synchronize()
-                what = (gx, gy, gz, v, grid)
+                what = (gx, gy, gz, v, grid, zseg)
                 if dtype == torch.float64:
                     assert torch.equal(a, b), what
                     assert torch.equal(fl_a, fl_b), what
