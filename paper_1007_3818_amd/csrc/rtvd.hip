@@ -42,7 +42,8 @@ struct RtvdLds {
 };
 
 // freezing speed c = |v_d| + c_s and the right/left-moving fluxes
-// fr = c (u + w), fl = c (u - w) with w = F_d(u) / c
+// fr = c (u + w), fl = c (u - w) with w = F_d(u) / c, evaluated as c u + F and
+// c u - F (the same values up to rounding, without the division by c)
 template <typename T>
 __device__ __forceinline__ void relax(const T u[NV], int d, T g, T gm1, T fr[NV], T fl[NV]) {
     const T ir = rcp(u[0]);
@@ -50,7 +51,6 @@ __device__ __forceinline__ void relax(const T u[NV], int d, T g, T gm1, T fr[NV]
     const T vd = d == 0 ? vx : (d == 1 ? vy : vz);
     const T p = gm1 * (u[4] - T(0.5) * (u[1] * vx + u[2] * vy + u[3] * vz));
     const T c = fabs(vd) + sqrt_(g * p * ir);
-    const T ic = rcp(c);
     T F[NV];
     F[0] = u[1 + d];
     F[1] = u[1] * vd;
@@ -60,9 +60,9 @@ __device__ __forceinline__ void relax(const T u[NV], int d, T g, T gm1, T fr[NV]
     F[4] = (u[4] + p) * vd;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const T w = F[v] * ic;
-        fr[v] = c * (u[v] + w);
-        fl[v] = c * (u[v] - w);
+        const T cu = c * u[v];
+        fr[v] = cu + F[v];
+        fl[v] = cu - F[v];
     }
 }
 
