@@ -179,9 +179,11 @@ int gamer_hydro_solve_batched_f32(const float *groups_in, int64_t n_groups, cons
  * (The paper's Sec. 2 notes that preparing ghost zones costs more than the GPU
  * solver itself; for this uniform case the preparation disappears.)  Results
  * equal those of gamer_pack_periodic followed by the batched step with the
- * same variant: bitwise in FP64, to rounding in FP32 (the two are separate
- * compilations, and float multiply-adds may contract differently).  dt_dev, dh_dev: device double [1].  state_out must not be
- * state.  group_stats, fluxes_out, opts as in the batched step.
+ * same variant: bitwise in FP64 with primitive limiting, to rounding otherwise
+ * (the two are separate compilations, whose multiply-adds may contract
+ * differently); fallback counts are equal.  dt_dev, dh_dev: device double
+ * [1].  state_out must not be state.  group_stats, fluxes_out, opts as in the
+ * batched step; opts->zseg as described with gamer_opts.
  * Errors: GAMER_EINVAL for gx, gy, gz outside [1, 2^24] or gx*gy*gz >= 2^31,
  * NULL state / state_out / dt_dev / dh_dev, state_out == state, gamma or opts
  * as in the batched step. */

@@ -6,7 +6,9 @@ Bars:
   * characteristic limiting: FP64 within 1e-12 of the oracle's characteristic
     limiting per cell (rho and E against the cell's own value, momenta against |m| + rho c_s), fallback counts exact, in every
     compiled variant; FP32 within 1e-5 in L1 per variable; the fused periodic
-    step bitwise equal to ghost fill + batched step in FP64;
+    step equal to ghost fill + batched step in FP64 within 1e-13 per cell (two
+    instantiations that may contract multiply-adds differently), with equal
+    fallback counts;
   * FP64 state, FP32 arithmetic: against the FP64 oracle within the FP32 bars
     (1e-5 relative on smooth flow, L1 1e-5 on the Mach-10 flow); within 1e-6 of
     the FP32 path on float-representable input; totals conserved over 20 steps
@@ -19,7 +21,7 @@ import torch
 import oracle
 from paper_1007_3818_amd import hydro, workloads as W
 from paper_1007_3818_amd.autotune import max_rel_diff
-from parity import flux_close, l1_rel, state_close
+from parity import flux_close, l1_rel, state_close, update_terms
 
 pytestmark = pytest.mark.gpu
 G53 = 5.0 / 3.0
@@ -56,9 +58,16 @@ def test_characteristic_limiting_fp64(gpu, name):
               f"{name} v{v} fluxes")
         s = stats.cpu().numpy()
         assert (int(s[:, 6].sum()), int(s[:, 7].sum())) == cnt
+        fstats = torch.empty((n, 8), dtype=torch.float64, device=gpu)
         fused = hydro.hydro_solve_periodic(st.to(gpu), gx, gy, gz, dev1(dt, gpu), dev1(dh, gpu), G53,
-                                           variant=v, limiting="characteristic")
-        assert torch.equal(fused, out)
+                                           variant=v, limiting="characteristic", group_stats=fstats)
+        # The periodic and padded instantiations of the characteristic-limiting
+        # kernel may contract different multiply-adds (measured: differences of
+        # at most 2.2e-16 of a cell's own scale on the smooth flow, 1e-14 on the
+        # log-normal one), so they agree to rounding, with exactly equal counts.
+        state_close(fused.cpu().numpy(), out.cpu().numpy(), 1e-13, f"{name} v{v} periodic vs padded",
+                    terms=update_terms(oracle.pack_periodic(host, gx, gy, gz), dt, dh))
+        assert torch.equal(fstats[:, 6:], stats[:, 6:])
     if name == "cosmo32":  # the limitings differ where waves interact (not from the
         assert np.abs(ref - prim).max() > 1e-8  # piecewise-constant Sod start: all slopes vanish)
 
