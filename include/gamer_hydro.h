@@ -349,8 +349,8 @@ int gamer_ctu_solve_batched_f32(const float *groups_in, int64_t n_groups, const 
  * work: device workspace of gamer_rtvd_workspace_bytes(n, f32) bytes, 16-byte
  * aligned, owned by the caller (nothing is allocated inside).  States with
  * rho <= 0 or p <= 0 are not caught (the scheme has no fallback).
- * Errors: GAMER_EINVAL for bad sizes or order, NULL or aliased arrays, a
- * missing or short workspace. */
+ * Errors: GAMER_EINVAL for bad sizes or order (periodic grids: gx <= 381300,
+ * gy, gz <= 65535), NULL or aliased arrays, a missing or short workspace. */
 size_t gamer_rtvd_workspace_bytes(int64_t n_groups, int f32);
 int gamer_rtvd_solve_batched(const double *groups_in, int64_t n_groups, const int8_t *level,
                              const double *dt_dev, const double *dh_dev, int n_levels, double gamma,

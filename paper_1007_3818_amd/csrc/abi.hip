@@ -405,6 +405,9 @@ int rtvd_periodic_common(const T *state, int gx, int gy, int gz, const double *d
     if (int64_t(gx) * NI > (1 << 28) || int64_t(gy) * NI > (1 << 28) || int64_t(gz) * NI > (1 << 28) ||
         n > INT32_MAX)
         return fail(GAMER_EINVAL, "grid too large: gx, gy, gz <= 2^24 and gx*gy*gz < 2^31 required");
+    // the first x sweep runs one grid row of 44 work-groups per group along x
+    if (gx > 381300 || gy > 65535 || gz > 65535)
+        return fail(GAMER_EINVAL, "grid too large for the relaxing TVD step: gx <= 381300, gy, gz <= 65535");
     return rtvd_common<T>(state, gx, gy, gz, n, nullptr, dt_dev, dh_dev, 1, gamma, order, work,
                           work_bytes, out);
 }

@@ -30,7 +30,6 @@ struct SweepArgs {
     int n_levels;     // a level byte outside [0, n_levels) gives the group NaN dt and dh
     double gamma;
     int64_t n_groups;
-    int tiles;        // work-groups per group
 };
 
 template <typename T>
@@ -82,22 +81,39 @@ __device__ __forceinline__ T vanleer_half(T x, T y) {
 // relaxed fluxes at positions 1..20, the second-order flux of each of the 17
 // faces once, and the update of the 16 output cells.  Consecutive lanes read
 // consecutive x, so the loads of a wave are contiguous along each pencil.
-template <typename T, bool PERIODIC>
+// E is the block's extent along y and z (22 for the first sweep of a step, 16
+// for the last), so every index below divides by a constant.  Work-groups: the
+// padded input runs a grid of TILES * XCHUNK by ceil(n / XCHUNK), group-major
+// within a row; the periodic input a grid of TILES * gx by gy by gz, one row
+// of tiles per group.
+template <int E>
+constexpr int x_tiles() { return (E * E + XPEN - 1) / XPEN; }
+constexpr int XCHUNK = 8192;  // groups per grid row of the padded-input x sweep
+
+template <typename T, int E, bool PERIODIC>
 __global__ __launch_bounds__(256) void rtvd_sweep_kernel(SweepArgs<T> P) {
+    constexpr int TILES = x_tiles<E>();
+    constexpr int VIN = RP * E * E, VOUT = NI * E * E;  // cells per variable, input and output
     __shared__ RtvdLds<T> S;
     const int t = threadIdx.x;
-    // 32-bit index arithmetic: the host caps the launch at 2^31 work-groups
-    const int gi = int(blockIdx.x / unsigned(P.tiles));
-    const int tile = int(blockIdx.x) - gi * P.tiles;
+    int gi, tile, bx = 0, by = 0, bz = 0;
+    if constexpr (PERIODIC) {
+        bx = int(blockIdx.x / unsigned(TILES));
+        tile = int(blockIdx.x) - bx * TILES;
+        by = int(blockIdx.y);
+        bz = int(blockIdx.z);
+        gi = bx + P.gx * (by + P.gy * bz);
+    } else {
+        const int gl = int(blockIdx.x / unsigned(TILES));
+        tile = int(blockIdx.x) - gl * TILES;
+        gi = int(blockIdx.y) * XCHUNK + gl;  // < 2^31: the host caps n_groups
+        if (gi >= P.n_groups) return;
+    }
     const int64_t g = gi;
-    if (g >= P.n_groups) return;
-    const int ex = P.ex, ey = P.ey, ez = P.ez;  // ex = 22
-    const int eox = ex - 2 * RG;
-    const int64_t vin = int64_t(ex) * ey * ez, vout = int64_t(eox) * ey * ez;
     const int q = t / RP, l = t - q * RP;  // pencil within the tile, position
     const int p = tile * XPEN + q;        // pencil index within the group: (y, z), y fastest
-    const bool live = q < XPEN && p < ey * ez;
-    const int iy = live ? p % ey : 0, iz = live ? p / ey : 0;
+    const bool live = q < XPEN && p < E * E;
+    const int iy = live ? p % E : 0, iz = live ? p / E : 0;
 
     double dt, dh;
     level_dt(P.level, g, P.n_levels, P.dt_dev, P.dh_dev, dt, dh);
@@ -111,7 +127,6 @@ __global__ __launch_bounds__(256) void rtvd_sweep_kernel(SweepArgs<T> P) {
         const T *src;
         int64_t vs;
         if constexpr (PERIODIC) {
-            const int bx = gi % P.gx, by = (gi / P.gx) % P.gy, bz = gi / (P.gx * P.gy);
             const int NX = P.gx * NI, NY = P.gy * NI, NZ = P.gz * NI;
             int X = bx * NI + l - RG, Y = by * NI + iy - RG, Z = bz * NI + iz - RG;
             X = X < 0 ? X + NX : (X >= NX ? X - NX : X);
@@ -121,8 +136,8 @@ __global__ __launch_bounds__(256) void rtvd_sweep_kernel(SweepArgs<T> P) {
             src = P.in + grp * GOUT + ((Z % NI) * NI + (Y % NI)) * NI + (X % NI);
             vs = NI * NI * NI;
         } else {
-            src = P.in + g * NV * vin + (int64_t(iz) * ey + iy) * ex + l;
-            vs = vin;
+            src = P.in + g * (NV * VIN) + (iz * E + iy) * RP + l;
+            vs = VIN;
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) S.u[v][q][l] = src[v * vs];
@@ -182,11 +197,11 @@ __global__ __launch_bounds__(256) void rtvd_sweep_kernel(SweepArgs<T> P) {
     // update of cell i = l + 3 (output position l)
     if (live && l < NI) {
         const int i = l + RG;
-        T *dst = P.out + g * NV * vout + (int64_t(iz) * ey + iy) * eox + l;
+        T *dst = P.out + g * (NV * VOUT) + (iz * E + iy) * NI + l;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const double o = double(S.u[v][q][i]) - hdtdx * (double(S.fc[v][q][i]) - double(S.fc[v][q][i - 1]));
-            dst[v * vout] = T(o);
+            dst[v * VOUT] = T(o);
         }
     }
 }
@@ -340,7 +355,6 @@ hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int
         P.gamma = gamma;
         P.n_groups = n;
         const int ta = d == 0 ? 1 : 0, tb = d == 2 ? 1 : 2;
-        P.tiles = (e[ta] * e[tb] + XPEN - 1) / XPEN;  // used by the x sweep
         if (d != 0) {
             // y and z pencils: one thread each, streaming (contiguous across the wave)
             if (n * e[ta] * e[tb] >= int64_t(1) << 31) return hipErrorInvalidValue;
@@ -354,13 +368,25 @@ hipError_t launch_rtvd(const T *in, int gx, int gy, int gz, int64_t n, const int
                 else hipLaunchKernelGGL((rtvd_stream_kernel<T, 2, false>), gr, bl, 0, s, P);
             }
         } else {
-            // x pencils: 11 per work-group through LDS, so that loads along x coalesce
-            const int64_t blocks = n * P.tiles;
-            if (blocks > int64_t(1) << 31) return hipErrorInvalidValue;
-            if (P.gx > 0)
-                hipLaunchKernelGGL((rtvd_sweep_kernel<T, true>), dim3(unsigned(blocks)), dim3(256), 0, s, P);
-            else
-                hipLaunchKernelGGL((rtvd_sweep_kernel<T, false>), dim3(unsigned(blocks)), dim3(256), 0, s, P);
+            // x pencils: 11 per work-group through LDS, so that loads along x coalesce;
+            // the block is 22 x E x E with E = 22 (first sweep) or 16 (last)
+            const int E = e[1];
+            const int64_t tiles = E == RP ? x_tiles<RP>() : x_tiles<NI>();
+            if (P.gx > 0) {
+                // periodic input: first sweep, E = 22; one row of tiles per group
+                if (int64_t(gx) * tiles * 256 >= int64_t(1) << 32 || gy > 65535 || gz > 65535)
+                    return hipErrorInvalidValue;
+                const dim3 gr(unsigned(gx * tiles), unsigned(gy), unsigned(gz));
+                hipLaunchKernelGGL((rtvd_sweep_kernel<T, RP, true>), gr, dim3(256), 0, s, P);
+            } else {
+                const int64_t rows = (n + XCHUNK - 1) / XCHUNK;
+                if (rows > 65535) return hipErrorInvalidValue;
+                const dim3 gr(unsigned(tiles * (n < XCHUNK ? n : XCHUNK)), unsigned(rows));
+                if (E == RP)
+                    hipLaunchKernelGGL((rtvd_sweep_kernel<T, RP, false>), gr, dim3(256), 0, s, P);
+                else
+                    hipLaunchKernelGGL((rtvd_sweep_kernel<T, NI, false>), gr, dim3(256), 0, s, P);
+            }
         }
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;

@@ -203,6 +203,10 @@ def test_rtvd_argument_errors(lib):
         assert f(P, 0, 2, 2, P, P, 1.4, 0, W, need, Q) == E
         assert f(P, 1 << 25, 1, 1, P, P, 1.4, 0, W, need, Q) == E
         assert f(P, 2, 2, 2, P, P, 1.4, 0, W, need, P) == E
+        # the first x sweep's grid: 44 work-groups per group along x, gy and gz as grid rows
+        for shape in ((381301, 1, 1), (1, 65536, 1), (1, 1, 65536)):
+            assert f(P, *shape, P, P, 1.4, 0, W, need, Q) == E
+            assert b"relaxing TVD" in lib.gamer_last_error()
 
 
 def test_periodic_argument_errors(lib):
