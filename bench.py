@@ -198,6 +198,29 @@ def bench_dtype(tag, state, g, dh, steps, warmup, workload, shape=None, pick=Non
     tot = totals.cpu().tolist()
     dt_used = float(dt_dev.item())
 
+    # the same step (solve + reduce) captured once in a HIP graph and replayed
+    progress(f"{tag}: timing HIP graph replays of the batched step")
+    gb = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(gb, stream=side):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    for _ in range(warmup):
+        gb.replay()
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        gb.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_gb = t0.elapsed_time(t1) / steps
+    graph_batched = {"ms_per_step": ms_gb, "cell_updates_per_s": n_groups * CELLS / (ms_gb * 1e-3),
+                     "dt_after": float(dt_dev.item()),
+                     "step": "the timed batched step (solve + reduce) captured in one HIP graph, replayed"}
+    del gb
+
     sample = None
     if pick is not None:
         # the timed configuration once more, at the input's own CFL time step
@@ -311,6 +334,7 @@ def bench_dtype(tag, state, g, dh, steps, warmup, workload, shape=None, pick=Non
                                    "grid evolving"},
         "with_ghost_fill": {"ms_per_step": ms_full, "cell_updates_per_s": cells / (ms_full * 1e-3),
                             "step": "periodic ghost fill + batched solve + reduce, grid evolving"},
+        "graph_replay_batched": graph_batched,
         **({"graph_replay": graph} if graph else {}),
         **({"fp64_state_fp32_arithmetic": mixed} if mixed else {}),
     }
