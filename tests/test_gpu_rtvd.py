@@ -6,7 +6,8 @@ runs on the float-rounded input); the periodic entry point (ghost cells read
 in place) equal to the padded one, bitwise in FP64, and against the oracle on
 grids one group thick along some axes; a uniform state kept
 bitwise; ten alternating FP64 steps of a smooth flow within 1e-11 of the
-oracle's ten steps.
+oracle's ten steps; a batch spanning two rows of the x sweep's launch grid
+equal, copy by copy, to its first copy.
 """
 import numpy as np
 import pytest
@@ -132,3 +133,28 @@ def test_workspace_checked(gpu):
     from paper_1007_3818_amd._native import GamerError
     with pytest.raises(GamerError):
         hydro.rtvd_solve_periodic(s, 2, 2, 2, dev1(1e-3, gpu), dev1(dh, gpu), G53, 0, work=small)
+
+
+def test_batch_over_several_grid_rows(gpu):
+    """The padded-input x sweep takes its group from a grid of 8192 groups per
+    row: a batch of 8,208 groups (1,026 copies of one 2 x 2 x 2 grid's padded
+    groups) spans two rows.  Every copy must equal the first bitwise, in both
+    sweep orders (the first x sweep on 22 x 22 pencils, the last on 16 x 16),
+    and the first copy must match the oracle within 1e-5 in L1 (FP32)."""
+    st, dh = W.smooth_modes(n=32, kmax=2, workload=2)
+    host32 = st.float().double().numpy()
+    pad_h = oracle.pack_periodic_rtvd(host32, 2, 2, 2)
+    dt = oracle.cfl_dt(host32, dh, G53, 0.4)
+    reps = 1026
+    pad = pad3_gpu(st.float().to(gpu), 2, 2, 2)
+    big = pad.repeat(reps, 1, 1, 1, 1)
+    print(f"[rtvd] batch of {big.shape[0]} padded groups (two grid rows of the x sweep)", flush=True)
+    for order in (0, 1):
+        out = hydro.rtvd_solve_batched(big, None, dev1(dt, gpu), dev1(dh, gpu), G53, order)
+        first = out[:8]
+        assert torch.equal(out.view(reps, 8, 5, 16, 16, 16), first.expand(reps, 8, 5, 16, 16, 16)), order
+        ref, _ = oracle.rtvd_solve(pad_h, dt, dh, G53, order)
+        l1 = l1_rel(first.cpu().double().numpy(), ref)
+        print(f"[parity] rtvd {reps} x 8 groups order {order}: L1 per variable {l1}", flush=True)
+        assert np.all(l1 < 1e-5), l1
+        del out
