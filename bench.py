@@ -709,6 +709,7 @@ def accuracy(samples, g, dh):
         r["oracle_fallbacks"] = list(cnt)
         r["groups"] = len(smp["pick"])
         r["bar"] = 1e-12 if tag == "f64" else 1e-5
+        r["within_bar"] = bool(r["max_rel_per_cell"] <= r["bar"])
         out[tag] = r
     if "f32" in samples and "f64" in samples:
         # the FP32 result against the oracle on the FP64 input (input rounding included)

@@ -127,6 +127,9 @@ def hydro_solve_batched(groups_in, level, dt_dev, dh_dev, gamma, out=None, fluxe
         _need(group_stats, (8,), torch.float64, "group_stats")
     n_levels = _levels(level, dt_dev, dh_dev, n)
     opts = _opts(theta, variant, grid, limiting, bad_count)
+    # torch's default stream has handle 0, which the call reads as "the thread's
+    # current library stream": make that torch's current stream as well
+    _stream()
     _native.check(fn(_ptr(groups_in), n, _ptr(level), _ptr(dt_dev), _ptr(dh_dev), n_levels,
                      float(gamma), _ptr(fluxes_out), _ptr(out), _ptr(group_stats),
                      ctypes.byref(opts) if opts is not None else None,

@@ -7,6 +7,8 @@
   * One group: the smallest ragged batch.  The float CTU sweep puts two groups
     in one work-group, so a one-group (or odd) batch runs with an empty second
     half; the result must still match the oracle and the pipeline variant.
+  * The batched call launches on torch's current stream, also after a call
+    made under another stream.
 """
 import ctypes
 
@@ -121,3 +123,27 @@ def test_one_group_ctu_both_variants(gpu, dtype):
                 terms=terms)
     assert (int(sa[0, 6]), int(sa[0, 7])) == cnt and np.array_equal(sa[:, 6:], sb[:, 6:])
     assert np.isfinite(sa).all()
+
+
+def test_batched_call_follows_torch_current_stream(gpu):
+    """hydro_solve_batched passes torch's current stream; torch's default stream
+    has handle 0, which the C call reads as the thread's library stream.  The
+    binding must set that stream too, or a call made on the default stream after
+    one made under another stream (a graph capture, say) would launch on the
+    other stream, unordered with the default stream's work."""
+    L = _native.lib()
+    st, dh = W.smooth_modes(n=32, kmax=2, workload=2)
+    s = st.to(gpu)
+    pad = hydro.pack_periodic(s, 2, 2, 2)
+    dt_dev = torch.tensor([0.2 * dh], dtype=torch.float64, device=gpu)
+    dh_dev = torch.tensor([dh], dtype=torch.float64, device=gpu)
+    ref = hydro.hydro_solve_batched(pad, None, dt_dev, dh_dev, G53)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        hydro.group_stats(s, G53)  # leaves the thread's library stream at `side`
+    side.synchronize()
+    assert (L.gamer_get_stream() or 0) == side.cuda_stream
+    out = hydro.hydro_solve_batched(pad, None, dt_dev, dh_dev, G53)  # torch's default stream
+    assert (L.gamer_get_stream() or 0) == torch.cuda.current_stream().cuda_stream
+    assert torch.equal(out, ref)
