@@ -161,7 +161,9 @@ int gamer_hydro_solve_f32(const float *groups_in, int64_t n_groups, double dt, d
  * [n_levels], 1 <= n_levels <= GAMER_MAX_LEVELS.  group_stats: device double
  * [n_groups][8] (see conventions) or NULL.  opts may be NULL.  hip_stream: the
  * hipStream_t to launch on, or NULL for the calling thread's current stream
- * (gamer_set_stream). */
+ * (gamer_set_stream).  The null stream's handle is NULL too, so a caller that
+ * means the null stream makes it the thread's stream first
+ * (gamer_set_stream(NULL)). */
 int gamer_hydro_solve_batched(const double *groups_in, int64_t n_groups, const int8_t *level,
                               const double *dt_dev, const double *dh_dev, int n_levels,
                               double gamma, double *fluxes_out, double *groups_out,
