@@ -277,8 +277,9 @@ __global__ __launch_bounds__(256) void rtvd_stream_kernel(SweepArgs<T> P) {
     constexpr int LSTR[3] = {1, NI, NI * NI};  // strides inside an unpadded group
 
     T u[RP][NV], fr[RP][NV], fl[RP][NV], fr2[RP][NV], fl2[RP][NV], Fc[RP][NV];
-#pragma unroll
-    for (int s = 0; s < RP; ++s) {
+    // cell s of the pencil into u[s]; issued PREFETCH cells ahead of its use,
+    // so that a wave's loads are in flight while it computes the cells before
+    auto load = [&](int s) {
         const T *src;
         if constexpr (PERIODIC) {
             const int q = s < RG ? 0 : (s < RG + NI ? 1 : 2);
@@ -289,6 +290,13 @@ __global__ __launch_bounds__(256) void rtvd_stream_kernel(SweepArgs<T> P) {
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) u[s][v] = src[v * vstride];
+    };
+    constexpr int PREFETCH = 2;  // 256^3 step: 0.976 -> 0.951 ms FP32, 1.757 -> 1.717 ms FP64
+#pragma unroll
+    for (int s = 0; s < PREFETCH; ++s) load(s);
+#pragma unroll
+    for (int s = 0; s < RP; ++s) {
+        if (s + PREFETCH < RP) load(s + PREFETCH);
         relax(u[s], D, g_, gm1, fr[s], fl[s]);
         if (s < 2) continue;
         // half-step state of cell m = s - 1 and its relaxed fluxes
