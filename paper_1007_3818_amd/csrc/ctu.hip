@@ -687,6 +687,14 @@ void ctu_fused(CtuArgs<T> P) {
             for (int v = 0; v < NV; ++v) S.a.ym[v][j + 1][i + 1] = um[v];
         }
         __syncthreads();  // B1: minus states of plane s and corrected plus states of plane kb
+        // the old state of the cell of plane kb that E updates, loaded before C so
+        // that the load overlaps the C phase instead of waiting in E (256^3 step:
+        // 1.357 -> 1.317 ms FP32, 3.347 -> 3.230 ms FP64)
+        T uold[NV];
+        if (mine && in_i && in_j && kb >= 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) uold[v] = U[v * (NP * NP * NP) + ((kb + NG) * NP + jj) * NP + ii];
+        }
 
         // ---- C: transverse x / y fluxes of plane s, final x / y fluxes of plane kb
         if (e1) {
@@ -761,7 +769,7 @@ void ctu_fused(CtuArgs<T> P) {
                     const double dxy = (double(S.a.fx[v][j][i + 1]) - double(S.a.fx[v][j][i])) +
                                        (double(S.a.fy[v][j + 1][i]) - double(S.a.fy[v][j][i]));
                     const double dfz = double(fz[v]) - double(fzb[v]);
-                    const double u0 = double(U[v * (NP * NP * NP) + ((kb + NG) * NP + jj) * NP + ii]);
+                    const double u0 = double(uold[v]);
                     const T o = T(u0 - hdtdh * (dxy + dfz));
                     out[v * (NI * NI * NI) + (kb * NI + j) * NI + i] = o;
                     un[v] = o;
