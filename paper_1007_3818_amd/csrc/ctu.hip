@@ -366,6 +366,13 @@ __global__ __launch_bounds__(256) void ctu_final(CtuArgs<T> P) {
         dxy[v] = 0.0;
     }
     for (int k = 0; k <= NI; ++k) {
+        // the old state of this column's cell in plane k - 1, loaded before the z
+        // face's solve so that its latency overlaps it
+        T uold[NV];
+        if (k >= 1) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) uold[v] = U[v * (NP * NP * NP) + ((k - 1 + NG) * NP + (j + NG)) * NP + (i + NG)];
+        }
         T fzn[NV];
         final_flux<2>(P, g, i, j, k, hdt, c, n_pred, n_roe, fzn);
         if (k >= 1) {
@@ -375,7 +382,7 @@ __global__ __launch_bounds__(256) void ctu_final(CtuArgs<T> P) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const double dfz = double(fzn[v]) - double(fz[v]);
-                const double u0 = double(U[v * (NP * NP * NP) + ((kk + NG) * NP + (j + NG)) * NP + (i + NG)]);
+                const double u0 = double(uold[v]);
                 const T o = T(u0 - dtdh * (dxy[v] + dfz));
                 out[v * (NI * NI * NI) + (kk * NI + j) * NI + i] = o;
                 un[v] = o;
