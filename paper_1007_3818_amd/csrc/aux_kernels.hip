@@ -7,9 +7,10 @@ namespace gamer {
 namespace {
 
 // ---- same-level periodic ghost fill --------------------------------------
-// One thread per padded row of 20 values along x: the 16 interior values come
-// from one contiguous source row (vector loads), the two ghost values on each
-// side from the periodic x neighbours; the row is written with vector stores.
+// float: one thread per padded row of 20 values along x: the 16 interior values
+// come from one contiguous source row (vector loads), the two ghost values on
+// each side from the periodic x neighbours; the row is written with vector
+// stores.
 template <typename T>
 struct Vec4;
 template <>
@@ -22,9 +23,8 @@ struct Vec4<double> {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void pack_periodic_kernel(const T *__restrict__ state, int gx,
-                                                            int gy, int gz, T *__restrict__ padded,
-                                                            int64_t n_rows) {
+__global__ __launch_bounds__(256) void pack_rows_kernel(const T *__restrict__ state, int gx, int gy,
+                                                        int gz, T *__restrict__ padded, int64_t n_rows) {
     using V = typename Vec4<T>::type;
     const int NY = gy * NI, NZ = gz * NI;
     for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n_rows;
@@ -56,6 +56,58 @@ __global__ __launch_bounds__(256) void pack_periodic_kernel(const T *__restrict_
         dst[2] = V{c1.z, c1.w, c2.x, c2.y};
         dst[3] = V{c2.z, c2.w, c3.x, c3.y};
         dst[4] = V{c3.z, c3.w, rgt[0], rgt[1]};
+    }
+}
+
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+
+// double: each padded row is written as five 4-value pieces, one thread each,
+// so that consecutive threads store consecutive 32-byte pieces (one thread per
+// row took 0.726 ms at 256^3 against 0.580 ms; in float, where a row is 80
+// bytes, the row per thread is the faster of the two, 0.297 against 0.329 ms).
+// Piece k of a padded row holds padded x = 4k - 2 .. 4k + 1: two pairs of
+// source values, from the left x neighbour (x = 14, 15) and the group's own row
+// for k = 0, from the own row and the right x neighbour (x = 0, 1) for k = 4,
+// and from the own row otherwise.
+template <typename T>
+__global__ __launch_bounds__(256) void pack_pieces_kernel(const T *__restrict__ state, int gx, int gy,
+                                                          int gz, T *__restrict__ padded, int64_t n_items) {
+    using V = typename Vec4<T>::type;
+    using V2 = typename Vec2<T>::type;
+    const int NY = gy * NI, NZ = gz * NI;
+    for (int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; r < n_items;
+         r += int64_t(gridDim.x) * blockDim.x) {
+        // r = (((g * 5 + v) * 20 + kp) * 20 + jp) * 5 + k
+        const int64_t row = r / 5;
+        const int k = int(r - row * 5);
+        const int jp = int(row % NP);
+        const int64_t r1 = row / NP;
+        const int kp = int(r1 % NP);
+        const int64_t r2 = r1 / NP;
+        const int v = int(r2 % NV);
+        const int g = int(r2 / NV);
+        const int bx = g % gx, by = (g / gx) % gy, bz = g / (gx * gy);
+        int Y = by * NI + jp - NG, Z = bz * NI + kp - NG;
+        Y = Y < 0 ? Y + NY : (Y >= NY ? Y - NY : Y);
+        Z = Z < 0 ? Z + NZ : (Z >= NZ ? Z - NZ : Z);
+        const int xa = k == 0 ? (bx == 0 ? gx - 1 : bx - 1) : bx;       // group of the first pair
+        const int xb = k == 4 ? (bx == gx - 1 ? 0 : bx + 1) : bx;       // group of the second pair
+        const int64_t grow = int64_t(gx) * (Y / NI + int64_t(gy) * (Z / NI));  // group of x block 0
+        const int64_t off = int64_t(v) * (NI * NI * NI) + (Z % NI) * (NI * NI) + (Y % NI) * NI;
+        // the pairs x0, x0 + 1 and x1, x1 + 1 of their source rows
+        const int x0 = k == 0 ? NI - 2 : 4 * k - 2, x1 = k == 4 ? 0 : 4 * k;
+        const V2 a = *reinterpret_cast<const V2 *>(state + (grow + xa) * GOUT + off + x0);
+        const V2 b = *reinterpret_cast<const V2 *>(state + (grow + xb) * GOUT + off + x1);
+        reinterpret_cast<V *>(padded + row * NP)[k] = V{a.x, a.y, b.x, b.y};
     }
 }
 
@@ -259,11 +311,16 @@ template <typename T>
 hipError_t launch_pack_periodic(const T *state, int gx, int gy, int gz, T *padded, hipStream_t s) {
     const int64_t n_rows = int64_t(gx) * gy * gz * NV * NP * NP;
     if (n_rows == 0) return hipSuccess;
-    int64_t blocks = (n_rows + 255) / 256;
+    const int64_t n_items = sizeof(T) == 4 ? n_rows : n_rows * 5;  // rows, or 4-value pieces
+    int64_t blocks = (n_items + 255) / 256;
     const int64_t cap = int64_t(256) * 2048;
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL(pack_periodic_kernel<T>, dim3(unsigned(blocks)), dim3(256), 0, s, state, gx,
-                       gy, gz, padded, n_rows);
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL(pack_rows_kernel<T>, dim3(unsigned(blocks)), dim3(256), 0, s, state, gx, gy, gz,
+                           padded, n_items);
+    else
+        hipLaunchKernelGGL(pack_pieces_kernel<T>, dim3(unsigned(blocks)), dim3(256), 0, s, state, gx, gy,
+                           gz, padded, n_items);
     return hipGetLastError();
 }
 
