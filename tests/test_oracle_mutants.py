@@ -4,13 +4,15 @@ Each case plants one plausible mistake in a temporary copy of the oracle's C
 sources, builds that copy with the oracle's own build function, and runs the
 pins that must catch the mistake in a child process whose `oracle` package
 loads the mutant library: the run must fail on a test, not on the build or on
-loading.  A control copy without a mistake must pass one pin file through the
+loading.  A control copy without a mistake must pass two pin files through the
 same route, so that a failing run is the mistake's doing.  The mistakes are the
 ones the pins were written against: the unsplit coupling of the Hancock
 predictor (Sec. 2, half-step prediction), the value and the sides of the
 Harten-Hyman entropy fix (Roe's solver), the limiter's central difference, the
 sign of Roe's dissipation, the predictor's half step, the relaxing scheme's
-half step and the CTU correction's sign.
+half step, the CTU correction's sign, and the coarse/fine correction's area
+average and sign and the restriction's average (the Python part of the oracle,
+loaded from the copy in place of `oracle.amr`).
 """
 import os
 import shutil
@@ -22,6 +24,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
 SOURCES = ("gamer_oracle.c", "gamer_rtvd.c", "gamer_ctu.c")
+PY_SOURCES = ("amr.py",)  # Python parts of the oracle, loaded from the copy in place of oracle.amr
 
 # (what the mistake is, file, [(text, replacement)], pins that must catch it)
 MUTANTS = [
@@ -52,6 +55,15 @@ MUTANTS = [
      "gamer_ctu.c", [("u[v] = dst[eidx(v, i, j, k)] - hdt * corr[v];",
                       "u[v] = dst[eidx(v, i, j, k)] + hdt * corr[v];")],
      ["tests/test_oracle_ctu.py"]),
+    ("coarse/fine correction with the fine fluxes averaged over 2 instead of 4 faces",
+     "amr.py", [("+ Ff[:, 1::2, 1::2]) / 4.0", "+ Ff[:, 1::2, 1::2]) / 2.0")],
+     ["tests/test_oracle_amr.py"]),
+    ("coarse/fine correction with its sign flipped on the wrong side",
+     "amr.py", [("if side == 1:\n                delta = -delta", "if side == 0:\n                delta = -delta")],
+     ["tests/test_oracle_amr.py"]),
+    ("restriction averaging over 4 instead of 8 fine cells",
+     "amr.py", [("= blk / 8.0", "= blk / 4.0")],
+     ["tests/test_oracle_amr.py"]),
 ]
 
 # Child process: point the oracle's build at the copy, build it (exit 3 if that
@@ -71,6 +83,12 @@ lib = oracle._lib()
 if os.path.realpath(lib._name) != os.path.realpath({lib!r}):
     print("LOADED", lib._name, flush=True)
     sys.exit(4)
+import importlib.util
+spec = importlib.util.spec_from_file_location("oracle.amr", {amr!r})
+mod = importlib.util.module_from_spec(spec)
+sys.modules["oracle.amr"] = mod
+spec.loader.exec_module(mod)
+oracle.amr = mod
 import pytest
 sys.exit(pytest.main(["-x", "-q", "-p", "no:cacheprovider", *{targets!r}]))
 """
@@ -79,7 +97,7 @@ sys.exit(pytest.main(["-x", "-q", "-p", "no:cacheprovider", *{targets!r}]))
 def _run(tmp_path, name, edits, targets):
     d = tmp_path / name
     d.mkdir()
-    for f in SOURCES:
+    for f in SOURCES + PY_SOURCES:
         shutil.copy(os.path.join(ORACLE, f), d / f)
     for fname, pairs in edits:
         p = d / fname
@@ -89,7 +107,8 @@ def _run(tmp_path, name, edits, targets):
             text = text.replace(old, new)
         p.write_text(text)
     lib = str(d / "libgamer_oracle_mutant.so")
-    code = DRIVER.format(root=ROOT, lib=lib, srcs=[str(d / f) for f in SOURCES], targets=targets)
+    code = DRIVER.format(root=ROOT, lib=lib, srcs=[str(d / f) for f in SOURCES], amr=str(d / "amr.py"),
+                         targets=targets)
     env = dict(os.environ, PYTHONDONTWRITEBYTECODE="1")
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
                        timeout=600)
@@ -97,7 +116,7 @@ def _run(tmp_path, name, edits, targets):
 
 
 def test_control_copy_passes(tmp_path):
-    rc, out = _run(tmp_path, "control", [], ["tests/test_oracle_pins.py"])
+    rc, out = _run(tmp_path, "control", [], ["tests/test_oracle_pins.py", "tests/test_oracle_amr.py"])
     assert rc == 0, out
 
 
