@@ -55,6 +55,19 @@ MUTANTS = [
      "gamer_ctu.c", [("u[v] = dst[eidx(v, i, j, k)] - hdt * corr[v];",
                       "u[v] = dst[eidx(v, i, j, k)] + hdt * corr[v];")],
      ["tests/test_oracle_ctu.py"]),
+    ("Roe averages weighted by density instead of its square root",
+     "gamer_oracle.c", [("double sl = sqrt(wl[0]), sr = sqrt(wr[0]);", "double sl = wl[0], sr = wr[0];")],
+     ["tests/test_oracle_pins.py"]),
+    ("HLLE's state-difference term with the states swapped",
+     "gamer_oracle.c", [("SL * SR * (R[m] - L[m])", "SL * SR * (L[m] - R[m])")],
+     ["tests/test_oracle_pins.py"]),
+    ("update reading the y fluxes with their transverse indices transposed",
+     "gamer_oracle.c", [("double dfy = FL(1, v, j + 1, k, i) - FL(1, v, j, k, i);",
+                         "double dfy = FL(1, v, j + 1, i, k) - FL(1, v, j, i, k);")],
+     ["tests/test_oracle_pins.py", "tests/test_oracle_unsplit.py", "tests/test_oracle_flows.py"]),
+    ("CFL signal speed with one sound speed instead of three",
+     "gamer_oracle.c", [("+ fabs(w[3]) + 3.0 * cs;", "+ fabs(w[3]) + cs;")],
+     ["tests/test_oracle_pins.py"]),
     ("coarse/fine correction with the fine fluxes averaged over 2 instead of 4 faces",
      "amr.py", [("+ Ff[:, 1::2, 1::2]) / 4.0", "+ Ff[:, 1::2, 1::2]) / 2.0")],
      ["tests/test_oracle_amr.py"]),
