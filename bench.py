@@ -78,12 +78,11 @@ CFL = 0.5
 SOLVER_SOURCES = ("solver.hip", "euler.h", "device_math.h", "internal.h")
 
 
-def read_traffic(tag, variant, grid, n_groups):
-    """HBM bytes per launch of the batched solver from the committed counter
-    summary, when it was taken on the current kernel sources, batch size and
-    launch shape; else None."""
+def read_profile_values(name):
+    """The `key = value` lines of a committed counter summary under profiles/,
+    or None when it is missing or was taken on other solver sources."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "solve_kernel_traffic_1024.md")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     h = hashlib.sha256()
@@ -97,9 +96,30 @@ def read_traffic(tag, variant, grid, n_groups):
             vals[k] = v
     if vals.get("solver_sources_sha256_16") != h.hexdigest()[:16]:
         return None
+    return vals
+
+
+def read_traffic(tag, variant, grid, n_groups):
+    """HBM bytes per launch of the batched solver from the committed counter
+    summary, when it was taken on the current kernel sources, batch size and
+    launch shape; else None."""
+    vals = read_profile_values("solve_kernel_traffic_1024.md")
+    if vals is None:
+        return None
     if vals.get("n_groups") != str(n_groups) or vals.get("shape") != f"{variant} {grid}":
         return None
     v = vals.get(f"bytes_per_launch_{tag}")
+    return float(v) if v else None
+
+
+def read_valu_lane_instr(tag, variant):
+    """VALU lane-instructions per cell-update of the default batched solver
+    (variant 0) from the committed SQ counter summary, when it was taken on the
+    current kernel sources; else None."""
+    vals = read_profile_values("solve_kernel_counters_256.md")
+    if vals is None or variant != 0:
+        return None
+    v = vals.get(f"valu_lane_instr_per_cell_{tag}")
     return float(v) if v else None
 
 
@@ -195,6 +215,14 @@ def bench_dtype(tag, state, g, dh, steps, warmup, workload, shape=None, pick=Non
         "hbm_achieved_GBps": bytes_per_group(elem) * n_groups / (k_ms * 1e-3) / 1e9,
         "hbm_frac": bytes_per_group(elem) * n_groups / (k_ms * 1e-3) / HBM_PEAK,
     }
+    # the share of the VALU issue ceiling (one wave64 instruction per 4 cycles per
+    # SIMD, 1,024 SIMDs at 2.4 GHz, no packed FP32) at the counted instructions
+    lane = read_valu_lane_instr(tag, variant)
+    if lane is not None:
+        ceiling = 1024 * 2.4e9 / 4 * 64 / lane  # cell-updates/s
+        roof["valu_lane_instr_per_cell"] = lane
+        roof["valu_issue_ceiling_cell_updates_per_s"] = ceiling
+        roof["valu_issue_frac"] = cells / (k_ms * 1e-3) / ceiling
     tot = totals.cpu().tolist()
     dt_used = float(dt_dev.item())
 
