@@ -10,7 +10,7 @@ ones the pins were written against: the unsplit coupling of the Hancock
 predictor (Sec. 2, half-step prediction), the value and the sides of the
 Harten-Hyman entropy fix (Roe's solver), the limiter's central difference, the
 sign of Roe's dissipation, the predictor's half step, the relaxing scheme's
-half step, the CTU correction's sign, and the coarse/fine correction's area
+half step, the CTU correction's sign, the characteristic limiter's projections, and the coarse/fine correction's area
 average and sign and the restriction's average (the Python part of the oracle,
 loaded from the copy in place of `oracle.amr`).
 """
@@ -68,6 +68,13 @@ MUTANTS = [
     ("CFL signal speed with one sound speed instead of three",
      "gamer_oracle.c", [("+ fabs(w[3]) + 3.0 * cs;", "+ fabs(w[3]) + cs;")],
      ["tests/test_oracle_pins.py"]),
+    ("characteristic limiting with the acoustic waves' velocity components swapped",
+     "gamer_oracle.c", [("dW[n] = c / rho * (m[4] - m[0]);", "dW[n] = c / rho * (m[0] - m[4]);")],
+     ["tests/test_oracle_char.py"]),
+    ("characteristic limiting with the entropy wave's pressure term added",
+     "gamer_oracle.c", [("la[1] = a[0] - a[4] / c2;", "la[1] = a[0] + a[4] / c2;"),
+                        ("lb[1] = b[0] - b[4] / c2;", "lb[1] = b[0] + b[4] / c2;")],
+     ["tests/test_oracle_char.py"]),
     ("coarse/fine correction with the fine fluxes averaged over 2 instead of 4 faces",
      "amr.py", [("+ Ff[:, 1::2, 1::2]) / 4.0", "+ Ff[:, 1::2, 1::2]) / 2.0")],
      ["tests/test_oracle_amr.py"]),
