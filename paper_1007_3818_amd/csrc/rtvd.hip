@@ -224,8 +224,17 @@ __global__ __launch_bounds__(256) void rtvd_stream_kernel(SweepArgs<T> P) {
     int eo[3] = {P.ex, P.ey, P.ez};
     eo[D] -= 2 * RG;
     const int ea = e[A], npen = e[A] * e[B];
-    // 32-bit index arithmetic: the host caps n_groups * pencils below 2^31
-    const int tid = int(blockIdx.x) * 256 + int(threadIdx.x);
+    // 32-bit index arithmetic: the host caps n_groups * pencils below 2^31.
+    // Work-groups go to the 8 XCDs round-robin (work-group b to XCD b mod 8),
+    // each with its own L2; the periodic first sweep numbers them so that each
+    // XCD takes a contiguous run of pencils, and so mostly whole groups with
+    // their x and y neighbours, whose cells it reads again as ghost cells.
+    int b = int(blockIdx.x);
+    if constexpr (PERIODIC) {
+        const int nb = int(gridDim.x), x = b % 8, j = b / 8, q = nb / 8, r = nb % 8;
+        b = x * q + (x < r ? x : r) + j;
+    }
+    const int tid = b * 256 + int(threadIdx.x);
     if (int64_t(tid) >= P.n_groups * npen) return;
     const int gi = tid / npen;
     const int p = tid - gi * npen;
